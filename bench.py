@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Throughput of the stencil library on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Headline (`value`): the full 2D stencil set on an 8192 x 8192 FP64 grid with
+c ~ U(-1, 1): the 4th-order 5-point second derivative in x and in y, the
+9-point cross derivative d4/dx2dy2 of Fig. 1 and the point-function stencil
+lap_h(c^3 - c), each periodic and non-periodic (output pre-zeroed): eight
+stencil applications per step, inputs resident in HBM.  Unit: grid points
+updated per second (8 x 8192^2 per step).
+
+The JSON line also carries the roofline of the dominant kernel (its average
+launch time taken with HIP events on the stream it runs on, against the
+algorithmic 16 bytes per point), the oracle timed on the host cores on a
+bounded sample, and further sections (FP32 stencil set, batched ragged 1D
+stencils) under "extra".  Only the cpu_baseline leg uses the oracle.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "stencil Gpoints/s + % HBM peak; CH ADI steps/s (FP64 vs FP32/batched)"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def stencil_set(wl, dx):
+    d2 = wl.scaled(wl.D2_4TH, 1.0 / dx ** 2)
+    return [("x_d2_4th", "X", (2, 2, 0, 0), d2, None),
+            ("y_d2_4th", "Y", (0, 0, 2, 2), d2, None),
+            ("xy_cross_fig1", "XY", (1, 1, 1, 1), wl.scaled(wl.CROSS_XXYY, 1.0 / dx ** 4), None),
+            ("lap_cubic_fun", "XY", (1, 1, 1, 1), wl.scaled(wl.LAPLACE_3X3, 1.0 / dx ** 2),
+             wl.CUBIC_MINUS_LINEAR)]
+
+
+def time_loop(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def bench_stencil_set(torch, b, wl, n, dt, steps, warmup):
+    """Returns (seconds per step, per-kernel average seconds, plans info)."""
+    tdt = {"f64": torch.float64, "f32": torch.float32}[dt]
+    code = {"f64": b.MXS_F64, "f32": b.MXS_F32}[dt]
+    dirs = {"X": b.MXS_X, "Y": b.MXS_Y, "XY": b.MXS_XY}
+    u = torch.from_numpy(wl.uniform_grid(n, n, seed=1)).to(tdt).cuda()
+    out = torch.zeros_like(u)
+    dx = 1.0 / n
+    plans = []
+    for name, d, ext, w, coe in stencil_set(wl, dx):
+        for periodic in (True, False):
+            L, R, T, B = ext
+            p = b.mxs_create_2d(n, n, n, dirs[d], b.MXS_P if periodic else b.MXS_NP, code,
+                                L, R, T, B, w, coe, u, out)
+            plans.append((f"{name}_{'p' if periodic else 'np'}", p))
+
+    def step():
+        for _, p in plans:
+            b.mxs_compute(p)
+
+    sec, wall = time_loop(torch, step, steps, warmup)
+    per_kernel = {}
+    for name, p in plans:
+        ks, _ = time_loop(torch, lambda: b.mxs_compute(p), max(steps, 10), 2)
+        per_kernel[name] = ks / max(steps, 10)
+    for _, p in plans:
+        b.mxs_destroy(p)
+    del u, out
+    torch.cuda.empty_cache()
+    return sec / steps, wall / steps, per_kernel, len(plans)
+
+
+def bench_ragged_1d(torch, b, wl, dt, steps, warmup):
+    tdt = {"f64": torch.float64, "f32": torch.float32}[dt]
+    code = {"f64": b.MXS_F64, "f32": b.MXS_F32}[dt]
+    lengths, offs = wl.ragged_lengths()
+    total = int(offs[-1])
+    v = torch.from_numpy(wl.ragged_values(total)).to(tdt).cuda()
+    o = torch.empty_like(v)
+    p = b.mxs_create_1d_batch(offs, b.MXS_P, code, 2, 2, list(wl.D1_4TH), None, v, o)
+    sec, _ = time_loop(torch, lambda: b.mxs_compute(p), steps, warmup)
+    b.mxs_destroy(p)
+    per = sec / steps
+    nbytes = 2 * total * v.element_size()
+    return {"points": total, "signals": int(len(lengths)), "s_per_pass": per,
+            "gpoints_per_s": total / per / 1e9, "gb_per_s": nbytes / per / 1e9,
+            "frac_hbm_peak": nbytes / per / 1e9 / HBM_PEAK_GBS}
+
+
+def cpu_baseline(wl, n, rows):
+    """The oracle (single thread) on the same eight stencils over a
+    rows x n slice of the grid."""
+    import oracle
+    u = wl.uniform_grid(rows, n, seed=1)
+    dx = 1.0 / n
+    t0 = time.perf_counter()
+    for name, d, ext, w, coe in stencil_set(wl, dx):
+        for periodic in (True, False):
+            oracle.stencil2d(u, *ext, w, periodic, coe=coe)
+    sec = time.perf_counter() - t0
+    pts = 8 * rows * n
+    return {"value": pts / sec / 1e9, "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
+            "sample": f"the eight stencils of one step on a {rows} x {n} slice "
+                      f"({pts} point updates, {sec:.1f} s, single-threaded C, "
+                      f"{os.cpu_count()} host cores visible)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1902_09931_amd import binding as b
+    from paper_1902_09931_amd import workloads as wl
+
+    n = args.n
+    log(f"device {torch.cuda.get_device_name(0)}; stencil set {n}^2 f64")
+    sec, wall, per_kernel, napps = bench_stencil_set(torch, b, wl, n, "f64", args.steps, args.warmup)
+    pts = napps * n * n
+    dominant = max(per_kernel, key=per_kernel.get)
+    bytes_per_launch = 2 * 8 * n * n
+    achieved = bytes_per_launch / per_kernel[dominant] / 1e9
+    result = {
+        "metric": METRIC,
+        "value": pts / sec / 1e9,
+        "unit": "Gpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D stencil set on a {n}x{n} FP64 grid, c~U(-1,1) seed 1: "
+                               "4th-order 5-point d2/dx2 and d2/dy2, Fig. 1 cross d4/dx2dy2, "
+                               "5-point Laplacian of c^3-c; periodic and non-periodic",
+                   "grid": [n, n], "stencil_applications_per_step": napps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": dominant, "avg_launch_us": per_kernel[dominant] * 1e6,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+    }
+    extra = {"wall_ms_per_step": wall * 1e3,
+             "f64_kernels_us": {k: v * 1e6 for k, v in per_kernel.items()},
+             "f64_hbm_frac_per_kernel": {k: bytes_per_launch / v / 1e9 / HBM_PEAK_GBS
+                                         for k, v in per_kernel.items()}}
+    if not args.no_extra:
+        log("stencil set f32")
+        s32, _, pk32, _ = bench_stencil_set(torch, b, wl, n, "f32", args.steps, args.warmup)
+        extra["f32_gpoints_per_s"] = pts / s32 / 1e9
+        extra["f32_kernels_us"] = {k: v * 1e6 for k, v in pk32.items()}
+        extra["f32_hbm_frac_per_kernel"] = {k: 2 * 4 * n * n / v / 1e9 / HBM_PEAK_GBS
+                                            for k, v in pk32.items()}
+        for dt in ("f64", "f32"):
+            log(f"ragged 1D {dt}")
+            extra[f"ragged1d_{dt}"] = bench_ragged_1d(torch, b, wl, dt, args.steps, args.warmup)
+    result["extra"] = extra
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(wl, n, rows=min(n, 3072))
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,165 @@
+// Internal declarations shared by the HIP kernels and the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace mxs {
+
+// ---------------------------------------------------------------------------
+// Storage types.  bfloat16 is carried as its 16 raw bits.
+// ---------------------------------------------------------------------------
+struct bf16 {
+    uint16_t bits;
+};
+
+enum Dtype { F64 = 0, F32 = 1, BF16 = 2 };
+
+inline int dtype_size(int dt) { return dt == F64 ? 8 : dt == F32 ? 4 : 2; }
+
+// Storage traits: accumulation type and elements per 8- or 16-byte vector.
+template <typename T> struct St;
+template <> struct St<double> { using acc = double; static constexpr int V = 2; };
+template <> struct St<float>  { using acc = float;  static constexpr int V = 4; };
+template <> struct St<bf16>   { using acc = float;  static constexpr int V = 4; };
+
+__device__ __forceinline__ float bf16_to_float(uint16_t b) {
+    return __uint_as_float(static_cast<uint32_t>(b) << 16);
+}
+
+// float -> bfloat16, round to nearest, ties to even; NaN stays NaN.
+__device__ __forceinline__ uint16_t float_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
+        return static_cast<uint16_t>((u >> 16) | 0x0040u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+
+template <typename T> __device__ __forceinline__ typename St<T>::acc to_acc(T v);
+template <> __device__ __forceinline__ double to_acc<double>(double v) { return v; }
+template <> __device__ __forceinline__ float to_acc<float>(float v) { return v; }
+template <> __device__ __forceinline__ float to_acc<bf16>(bf16 v) { return bf16_to_float(v.bits); }
+
+template <typename T> __device__ __forceinline__ T from_acc(typename St<T>::acc v);
+template <> __device__ __forceinline__ double from_acc<double>(double v) { return v; }
+template <> __device__ __forceinline__ float from_acc<float>(float v) { return v; }
+template <> __device__ __forceinline__ bf16 from_acc<bf16>(float v) { return bf16{float_to_bf16(v)}; }
+
+// Vector load/store of St<T>::V consecutive elements (16 bytes for double and
+// float, 8 bytes for bf16).  The address must be aligned to the vector size.
+template <typename T>
+__device__ __forceinline__ void load_vec(const T *p, typename St<T>::acc *x);
+template <>
+__device__ __forceinline__ void load_vec<double>(const double *p, double *x) {
+    double2 v = *reinterpret_cast<const double2 *>(p);
+    x[0] = v.x; x[1] = v.y;
+}
+template <>
+__device__ __forceinline__ void load_vec<float>(const float *p, float *x) {
+    float4 v = *reinterpret_cast<const float4 *>(p);
+    x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void load_vec<bf16>(const bf16 *p, float *x) {
+    uint2 v = *reinterpret_cast<const uint2 *>(p);
+    x[0] = __uint_as_float(v.x << 16); x[1] = __uint_as_float(v.x & 0xffff0000u);
+    x[2] = __uint_as_float(v.y << 16); x[3] = __uint_as_float(v.y & 0xffff0000u);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_vec(T *p, const typename St<T>::acc *x);
+template <>
+__device__ __forceinline__ void store_vec<double>(double *p, const double *x) {
+    *reinterpret_cast<double2 *>(p) = make_double2(x[0], x[1]);
+}
+template <>
+__device__ __forceinline__ void store_vec<float>(float *p, const float *x) {
+    *reinterpret_cast<float4 *>(p) = make_float4(x[0], x[1], x[2], x[3]);
+}
+template <>
+__device__ __forceinline__ void store_vec<bf16>(bf16 *p, const float *x) {
+    uint2 v;
+    v.x = static_cast<uint32_t>(float_to_bf16(x[0])) | (static_cast<uint32_t>(float_to_bf16(x[1])) << 16);
+    v.y = static_cast<uint32_t>(float_to_bf16(x[2])) | (static_cast<uint32_t>(float_to_bf16(x[3])) << 16);
+    *reinterpret_cast<uint2 *>(p) = v;
+}
+
+__device__ __forceinline__ long long wrap_ll(long long k, long long n) {
+    long long r = k % n;
+    return r < 0 ? r + n : r;
+}
+
+// Point function f(c) = sum_m coe[m] c^m by Horner's rule; identity when
+// ncoe == 0.
+template <typename A>
+__device__ __forceinline__ A point_fun(A c, const A *coe, int ncoe) {
+    if (ncoe == 0) return c;
+    A f = coe[ncoe - 1];
+    for (int m = ncoe - 2; m >= 0; --m) f = f * c + coe[m];
+    return f;
+}
+
+// Map a workgroup index to a tile index so that the workgroups the hardware
+// sends to one XCD (round robin: block b goes to XCD b % 8) cover one
+// contiguous range of tiles.  A bijection on [0, n).
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    const int q = n >> 3, r = n & 7;
+    const int x = b & 7, k = b >> 3;
+    const int base = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+    return base + k;
+}
+
+constexpr int kMaxCoe = 8;
+
+// ---------------------------------------------------------------------------
+// 2D stencil launch arguments.
+// ---------------------------------------------------------------------------
+struct Stencil2DArgs {
+    const void *in;
+    void *out;
+    long long ld;
+    int nx, ny;
+    int L, R, T, B;         // actual extents
+    int periodic;
+    int ncoe;
+    const void *wts;        // device, NWY x NWX padded weights in the accumulation type
+    double coe_d[kMaxCoe];
+    float coe_f[kMaxCoe];
+    int rows;               // output rows per workgroup
+    int nchunks;            // row chunks per strip
+    int nstrips;            // column strips
+    int vec_ok;             // 16-byte (8-byte for bf16) aligned rows
+};
+
+struct Stencil1DArgs {
+    const void *in;
+    void *out;
+    const long long *offsets;   // device, nbatch + 1
+    const int *tile_first;      // device, ntiles + 1: first signal of each tile
+    long long total;
+    int nbatch;
+    int ntiles;
+    int L, R;
+    int periodic;
+    int ncoe;
+    const void *wts;            // device, NWX padded weights
+    double coe_d[kMaxCoe];
+    float coe_f[kMaxCoe];
+    int max_sig_per_tile;       // LDS slots reserved for offsets
+    int vec_ok;
+};
+
+// Window buckets: padded widths the kernels are compiled for.
+int bucket_width(int taps);   // 1, 3, 5, 9 or 17; 0 if too wide
+
+hipError_t launch_stencil2d(int dtype, int nwx, int nwy, const Stencil2DArgs &a,
+                            int threads, hipStream_t s);
+hipError_t launch_stencil1d(int dtype, int nwx, const Stencil1DArgs &a, int threads,
+                            int grid, hipStream_t s);
+size_t stencil2d_lds_bytes(int dtype, int nwx, int nwy, int threads);
+size_t stencil1d_lds_bytes(int dtype, int nwx, int threads, int max_sig);
+
+}  // namespace mxs

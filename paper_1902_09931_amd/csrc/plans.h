@@ -1,0 +1,46 @@
+// Plan objects behind the opaque mxs_plan handle, and helpers of the C ABI.
+#pragma once
+
+#include "mxs_internal.h"
+#include "mxsten.h"
+
+#include <stddef.h>
+
+enum PlanKind { KIND_STENCIL2D = 1, KIND_STENCIL1D = 2, KIND_SOLVE = 3, KIND_CH = 4 };
+
+struct mxs_plan_s {
+    int kind;
+    explicit mxs_plan_s(int k) : kind(k) {}
+    virtual ~mxs_plan_s() {}
+    virtual mxs_status compute(hipStream_t) { return MXS_ERR_BAD_HANDLE; }
+    virtual mxs_status swap() { return MXS_ERR_BAD_HANDLE; }
+    virtual mxs_status rebind(const void *, void *) { return MXS_ERR_BAD_HANDLE; }
+};
+
+namespace mxs {
+
+// Device allocation owned by a plan.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf();
+    void reset();
+    hipError_t alloc(size_t n);
+    hipError_t upload(const void *src, size_t n);
+};
+
+mxs_status fail(mxs_status st, const char *fmt, ...);
+mxs_status hip_fail(hipError_t e, const char *what);
+void register_plan(const mxs_plan_s *p);
+bool unregister_plan(const mxs_plan_s *p);
+bool is_live(const mxs_plan_s *p);
+bool ranges_overlap(const void *a, size_t abytes, const void *b, size_t bbytes);
+size_t grid_bytes(int nx, int ny, long long ld, int dtype);
+int device_lds_limit();
+int device_cu_count();
+bool valid_dtype(int d);
+
+}  // namespace mxs

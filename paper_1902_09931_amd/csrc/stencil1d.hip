@@ -1,0 +1,175 @@
+// Batched 1D stencils over uneven signals stored back to back (the batched
+// 1D form of the abstract).
+//
+// The concatenated array is cut into equal tiles of W = threads * V elements,
+// regardless of where signals begin and end, so every workgroup moves the
+// same number of bytes whatever the length mix.  A persistent grid walks
+// the tiles.  For each tile the workgroup stages the values (plus an x halo
+// of PAD elements each side) and the slice of signal offsets that meets the
+// tile in LDS.  Each output finds its signal by binary search in that slice.
+// Outputs whose window stays inside their signal read LDS directly; the few
+// near a signal end wrap within the signal (periodic) and read the wrapped
+// value from LDS when it is staged, else from global memory.
+#include "mxs_internal.h"
+
+namespace mxs {
+
+namespace {
+
+template <typename A> __device__ __forceinline__ const A *coe_of(const Stencil1DArgs &a);
+template <> __device__ __forceinline__ const double *coe_of<double>(const Stencil1DArgs &a) { return a.coe_d; }
+template <> __device__ __forceinline__ const float *coe_of<float>(const Stencil1DArgs &a) { return a.coe_f; }
+
+template <int NWX, int V> constexpr int halo_pad() {
+    return NWX > 1 ? ((NWX - 1 + V - 1) / V) * V : 0;
+}
+
+template <typename T, int NWX>
+__global__ void __launch_bounds__(256) stencil1d_kernel(const Stencil1DArgs a) {
+    using A = typename St<T>::acc;
+    constexpr int V = St<T>::V;
+    constexpr int PAD = halo_pad<NWX, V>();
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int nt = blockDim.x;
+    const int t = threadIdx.x;
+    const int W = nt * V;
+    A *lds = reinterpret_cast<A *>(smem_raw);
+    long long *soff = reinterpret_cast<long long *>(smem_raw + ((static_cast<size_t>(2 * PAD + W) * sizeof(A) + 15) & ~static_cast<size_t>(15)));
+
+    const T *__restrict__ in = static_cast<const T *>(a.in);
+    T *__restrict__ out = static_cast<T *>(a.out);
+    const A *__restrict__ w = static_cast<const A *>(a.wts);
+    const A *coe = coe_of<A>(a);
+    const bool periodic = a.periodic != 0;
+    const int taps = a.L + a.R + 1;
+
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        const long long e0 = static_cast<long long>(tile) * W;
+        const int b0 = a.tile_first[tile];
+        const int cnt = a.tile_first[tile + 1] - b0 + 2;   // offsets b0 .. b_last+1
+
+        __syncthreads();   // LDS of the previous tile is no longer read
+        for (int k = t; k < cnt; k += nt) soff[k] = a.offsets[b0 + k];
+
+        const long long eb = e0 + static_cast<long long>(t) * V;
+        A xv[V];
+        if (a.vec_ok && eb + V <= a.total) {
+            load_vec<T>(in + eb, xv);
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) xv[v] = eb + v < a.total ? to_acc<T>(in[eb + v]) : A(0);
+        }
+        if (a.ncoe) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) xv[v] = point_fun<A>(xv[v], coe, a.ncoe);
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) lds[PAD + t * V + v] = xv[v];
+        for (int h = t; h < 2 * PAD; h += nt) {
+            const long long c = h < PAD ? e0 - PAD + h : e0 + W + (h - PAD);
+            A val = A(0);
+            if (c >= 0 && c < a.total) {
+                val = to_acc<T>(in[c]);
+                if (a.ncoe) val = point_fun<A>(val, coe, a.ncoe);
+            }
+            lds[h < PAD ? h : W + h] = val;
+        }
+        __syncthreads();
+
+        A res[V];
+        bool wr[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const long long e = eb + v;
+            res[v] = A(0);
+            wr[v] = false;
+            if (e >= a.total) continue;
+            int lo = 0, hi = cnt - 2;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (soff[mid] <= e) lo = mid; else hi = mid - 1;
+            }
+            const long long sb = soff[lo];
+            const long long n = soff[lo + 1] - sb;
+            const long long i = e - sb;
+            if (!periodic && (i < a.L || i > n - 1 - a.R)) continue;
+            wr[v] = true;
+            A acc = A(0);
+            if (i >= a.L && i - a.L + (NWX - 1) <= n - 1) {
+                const A *lp = lds + PAD + (e - e0) - a.L;
+#pragma unroll
+                for (int p = 0; p < NWX; ++p) acc = fma(w[p], lp[p], acc);
+            } else {
+                for (int p = 0; p < taps; ++p) {
+                    long long ii = i + p - a.L;
+                    if (ii < 0) ii += n;
+                    else if (ii >= n) ii -= n;
+                    const long long idx = sb + ii;
+                    A val;
+                    if (idx >= e0 - PAD && idx < e0 + W + PAD) {
+                        val = lds[PAD + (idx - e0)];
+                    } else {
+                        val = to_acc<T>(in[idx]);
+                        if (a.ncoe) val = point_fun<A>(val, coe, a.ncoe);
+                    }
+                    acc = fma(w[p], val, acc);
+                }
+            }
+            res[v] = acc;
+        }
+        bool all = a.vec_ok && eb + V <= a.total;
+#pragma unroll
+        for (int v = 0; v < V; ++v) all = all && wr[v];
+        if (all) {
+            store_vec<T>(out + eb, res);
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                if (wr[v]) out[eb + v] = from_acc<T>(res[v]);
+        }
+    }
+}
+
+template <typename T, int NWX>
+hipError_t launch_one(const Stencil1DArgs &a, int threads, int grid, hipStream_t s) {
+    const size_t lds = stencil1d_lds_bytes(std::is_same<T, double>::value ? F64
+                                           : std::is_same<T, float>::value ? F32 : BF16,
+                                           NWX, threads, a.max_sig_per_tile);
+    hipLaunchKernelGGL((stencil1d_kernel<T, NWX>), dim3(grid), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch(int nwx, const Stencil1DArgs &a, int threads, int grid, hipStream_t s) {
+    switch (nwx) {
+    case 1: return launch_one<T, 1>(a, threads, grid, s);
+    case 3: return launch_one<T, 3>(a, threads, grid, s);
+    case 5: return launch_one<T, 5>(a, threads, grid, s);
+    case 9: return launch_one<T, 9>(a, threads, grid, s);
+    case 17: return launch_one<T, 17>(a, threads, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+size_t stencil1d_lds_bytes(int dtype, int nwx, int threads, int max_sig) {
+    const int V = dtype == F64 ? St<double>::V : dtype == F32 ? St<float>::V : St<bf16>::V;
+    const int acc = dtype == F64 ? 8 : 4;
+    const int pad = nwx > 1 ? ((nwx - 1 + V - 1) / V) * V : 0;
+    const size_t vals = (static_cast<size_t>(2 * pad + threads * V) * acc + 15) & ~static_cast<size_t>(15);
+    return vals + static_cast<size_t>(max_sig) * sizeof(long long);
+}
+
+hipError_t launch_stencil1d(int dtype, int nwx, const Stencil1DArgs &a, int threads, int grid,
+                            hipStream_t s) {
+    switch (dtype) {
+    case F64: return dispatch<double>(nwx, a, threads, grid, s);
+    case F32: return dispatch<float>(nwx, a, threads, grid, s);
+    case BF16: return dispatch<bf16>(nwx, a, threads, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mxs

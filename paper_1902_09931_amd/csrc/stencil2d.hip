@@ -1,0 +1,260 @@
+// 2D stencils in the x, y and xy directions, periodic or non-periodic, with
+// fixed weights or a point function (Sec. 3, Sec. 4.1, Sec. 4.2).
+//
+// One kernel template covers every direction.  A workgroup owns a strip of
+// W = threads * V columns and a chunk of `rows` output rows.  It streams the
+// input rows of its chunk top to bottom; each thread keeps, per pending
+// output row, an accumulator vector of V outputs in registers (NWY rows,
+// shifted by one row as each output row completes).  When an input row arrives, its window along x (V + NWX - 1 values,
+// read from an LDS copy of the row with its x halo, or straight from
+// registers when NWX == 1) is multiplied into every pending output row it
+// touches; the output row whose window is complete is written out.  Each
+// input element is therefore read from HBM once per chunk (plus the NWY - 1
+// halo rows shared with the chunk above), and each output element written
+// once, with 8- or 16-byte vector accesses.
+//
+// The window is padded to the compiled widths NWX x NWY in {1,3,5,9,17};
+// padded taps carry weight zero.  Weights live in device memory in the
+// accumulation type and are read with uniform (scalar) loads.
+#include "mxs_internal.h"
+
+#include <type_traits>
+
+namespace mxs {
+
+namespace {
+
+template <int NWX, int V> constexpr int halo_pad() {
+    return NWX > 1 ? ((NWX - 1 + V - 1) / V) * V : 0;
+}
+
+// Input rows loaded per round (into LDS when NWX > 1).
+template <int NWY> constexpr int stage_rows() {
+    return 4;
+}
+
+template <typename A> __device__ __forceinline__ const A *coe_of(const Stencil2DArgs &a);
+template <> __device__ __forceinline__ const double *coe_of<double>(const Stencil2DArgs &a) { return a.coe_d; }
+template <> __device__ __forceinline__ const float *coe_of<float>(const Stencil2DArgs &a) { return a.coe_f; }
+
+// Load element c of an input row, wrapping (periodic) or as zero when outside
+// [0, nx) (non-periodic: such values never reach a written output).
+template <typename T>
+__device__ __forceinline__ typename St<T>::acc load_elem(const T *rowp, long long c, int nx,
+                                                         bool periodic) {
+    using A = typename St<T>::acc;
+    if (c < 0 || c >= nx) {
+        if (!periodic) return A(0);
+        c = wrap_ll(c, nx);
+    }
+    return to_acc<T>(rowp[c]);
+}
+
+template <typename T, int NWX, int NWY>
+__global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
+    using A = typename St<T>::acc;
+    constexpr int V = St<T>::V;
+    constexpr int PAD = halo_pad<NWX, V>();
+    constexpr int G = stage_rows<NWY>();
+    constexpr int XW = V + NWX - 1;
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    A *lds = reinterpret_cast<A *>(smem_raw);
+
+    const T *__restrict__ in = static_cast<const T *>(a.in);
+    T *__restrict__ out = static_cast<T *>(a.out);
+    const A *__restrict__ w = static_cast<const A *>(a.wts);
+    const A *coe = coe_of<A>(a);
+
+    const int nt = blockDim.x;
+    const int t = threadIdx.x;
+    const int W = nt * V;
+    const int rowlen = PAD + W + PAD;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int strip = tile / a.nchunks;
+    const int chunk = tile - strip * a.nchunks;
+    const long long i0 = static_cast<long long>(strip) * W;
+    const int j0 = chunk * a.rows;
+    const int H = min(a.rows, a.ny - j0);
+    const int niter = H + NWY - 1;
+    const long long ib = i0 + static_cast<long long>(t) * V;
+    const bool periodic = a.periodic != 0;
+    const bool full_vec = a.vec_ok && (ib + V <= a.nx);
+    const bool store_vec_ok = full_vec && (periodic || (ib >= a.L && ib + V - 1 <= a.nx - 1 - a.R));
+
+    A acc[NWY][V];
+#pragma unroll
+    for (int q = 0; q < NWY; ++q)
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[q][v] = A(0);
+
+    for (int s0 = 0; s0 < niter; s0 += G) {
+        // ---- load G input rows (V elements per thread) ------------------
+        A xin[G][V];
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int s = s0 + u;
+            long long r = static_cast<long long>(j0) - a.T + s;
+            bool rv = s < niter;
+            if (periodic) r = wrap_ll(r, a.ny);
+            else rv = rv && r >= 0 && r < a.ny;
+            if (rv) {
+                const T *rowp = in + r * a.ld;
+                if (full_vec) {
+                    load_vec<T>(rowp + ib, xin[u]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) xin[u][v] = load_elem<T>(rowp, ib + v, a.nx, periodic);
+                }
+                if (a.ncoe) {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) xin[u][v] = point_fun<A>(xin[u][v], coe, a.ncoe);
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v) xin[u][v] = A(0);
+            }
+        }
+
+        // ---- stage the rows and their x halo in LDS ----------------------
+        if constexpr (NWX > 1) {
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                A *dst = lds + u * rowlen + PAD + t * V;
+#pragma unroll
+                for (int v = 0; v < V; ++v) dst[v] = xin[u][v];
+            }
+            for (int h = t; h < G * 2 * PAD; h += nt) {
+                const int u = h / (2 * PAD);
+                const int hh = h - u * 2 * PAD;
+                const long long c = hh < PAD ? i0 - PAD + hh : i0 + W + (hh - PAD);
+                const int s = s0 + u;
+                long long r = static_cast<long long>(j0) - a.T + s;
+                bool rv = s < niter;
+                if (periodic) r = wrap_ll(r, a.ny);
+                else rv = rv && r >= 0 && r < a.ny;
+                A val = A(0);
+                if (rv) {
+                    val = load_elem<T>(in + r * a.ld, c, a.nx, periodic);
+                    if (a.ncoe) val = point_fun<A>(val, coe, a.ncoe);
+                }
+                lds[u * rowlen + (hh < PAD ? hh : W + hh)] = val;
+            }
+            __syncthreads();
+        }
+
+        // ---- accumulate and emit completed rows ----------------------------
+        // acc[k] holds output row s - (NWY-1) + k; input row s meets it with
+        // window row NWY-1-k.  After the row, acc[0] is complete: it is
+        // written and the window shifts by one row.
+        auto consume = [&](const A *x, int s) {
+#pragma unroll
+            for (int k = 0; k < NWY; ++k) {
+#pragma unroll
+                for (int p = 0; p < NWX; ++p) {
+                    const A wt = w[(NWY - 1 - k) * NWX + p];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) acc[k][v] = fma(wt, x[v + p], acc[k][v]);
+                }
+            }
+            const int jj = s - (NWY - 1);
+            if (jj >= 0 && jj < H) {
+                const int j = j0 + jj;
+                if (periodic || (j >= a.T && j <= a.ny - 1 - a.B)) {
+                    T *rowp = out + static_cast<long long>(j) * a.ld;
+                    if (store_vec_ok) {
+                        store_vec<T>(rowp + ib, acc[0]);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            const long long c = ib + v;
+                            if (c < a.nx && (periodic || (c >= a.L && c <= a.nx - 1 - a.R)))
+                                rowp[c] = from_acc<T>(acc[0][v]);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k + 1 < NWY; ++k)
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[k][v] = acc[k + 1][v];
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[NWY - 1][v] = A(0);
+        };
+
+        if constexpr (NWX > 1) {
+            const int nu = min(G, niter - s0);
+#pragma unroll 1
+            for (int u = 0; u < nu; ++u) {
+                A x[XW];
+                const A *lp = lds + u * rowlen + PAD + t * V - a.L;
+#pragma unroll
+                for (int k = 0; k < XW; ++k) x[k] = lp[k];
+                consume(x, s0 + u);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < G; ++u)
+                if (s0 + u < niter) consume(xin[u], s0 + u);
+        }
+    }
+}
+
+template <typename T, int NWX, int NWY>
+hipError_t launch_one(const Stencil2DArgs &a, int threads, hipStream_t s) {
+    using A = typename St<T>::acc;
+    constexpr int V = St<T>::V;
+    const size_t lds = NWX > 1
+        ? static_cast<size_t>(stage_rows<NWY>()) * (2 * halo_pad<NWX, V>() + threads * V) * sizeof(A)
+        : 0;
+    const int grid = a.nstrips * a.nchunks;
+    hipLaunchKernelGGL((stencil2d_kernel<T, NWX, NWY>), dim3(grid), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch(int nwx, int nwy, const Stencil2DArgs &a, int threads, hipStream_t s) {
+#define MXS_CASE(X, Y) \
+    if (nwx == X && nwy == Y) return launch_one<T, X, Y>(a, threads, s);
+    MXS_CASE(1, 1) MXS_CASE(3, 1) MXS_CASE(5, 1) MXS_CASE(9, 1) MXS_CASE(17, 1)
+    MXS_CASE(1, 3) MXS_CASE(1, 5) MXS_CASE(1, 9) MXS_CASE(1, 17)
+    MXS_CASE(3, 3) MXS_CASE(3, 5) MXS_CASE(3, 9)
+    MXS_CASE(5, 3) MXS_CASE(5, 5) MXS_CASE(5, 9)
+    MXS_CASE(9, 3) MXS_CASE(9, 5) MXS_CASE(9, 9)
+#undef MXS_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int bucket_width(int taps) {
+    if (taps <= 1) return 1;
+    if (taps <= 3) return 3;
+    if (taps <= 5) return 5;
+    if (taps <= 9) return 9;
+    if (taps <= 17) return 17;
+    return 0;
+}
+
+size_t stencil2d_lds_bytes(int dtype, int nwx, int nwy, int threads) {
+    if (nwx <= 1) return 0;
+    const int V = dtype == F64 ? St<double>::V : dtype == F32 ? St<float>::V : St<bf16>::V;
+    const int acc = dtype == F64 ? 8 : 4;
+    const int pad = ((nwx - 1 + V - 1) / V) * V;
+    const int g = 4;
+    (void)nwy;
+    return static_cast<size_t>(g) * (2 * pad + threads * V) * acc;
+}
+
+hipError_t launch_stencil2d(int dtype, int nwx, int nwy, const Stencil2DArgs &a, int threads,
+                            hipStream_t s) {
+    switch (dtype) {
+    case F64: return dispatch<double>(nwx, nwy, a, threads, s);
+    case F32: return dispatch<float>(nwx, nwy, a, threads, s);
+    case BF16: return dispatch<bf16>(nwx, nwy, a, threads, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mxs
