@@ -1,0 +1,44 @@
+// ADI Cahn-Hilliard step: structures shared by the kernels and the plan.
+#pragma once
+
+#include "mxs_internal.h"
+
+namespace mxs {
+
+// Right-hand side of the x sweep (Sec. 5.1), per instance:
+//   R = cdiff (C^n - C^{n-1}) + sum wb * Cbar + sum wl * (C^n^3 - C^n),
+//   Cbar = 2 C^n - C^{n-1}; wb is the 5x5 biharmonic window scaled by
+//   -2/3 D gamma dt, wl the 3x3 Laplacian window scaled by 2/3 D dt, and
+//   cdiff = -2/3.
+struct RhsInst {
+    const void *cur;     // C^n, state dtype
+    const void *prev;    // C^{n-1}, state dtype
+    void *R;             // right-hand side, w dtype
+    int nx, ny;          // pitch == nx
+    int nstrips, nchunks, rows;
+    int blk0;            // first block of this instance
+    double wb[25];
+    double wl[9];
+    double cdiff;
+    float wbf[25];
+    float wlf[9];
+    float cdifff;
+};
+
+constexpr int kRhsThreads = 256;
+
+// One launch over every instance of the table.
+hipError_t launch_ch_rhs(int state_dtype, const RhsInst *inst, int ninst, int blocks,
+                         hipStream_t s);
+
+// Mass: per-instance double sums of a state buffer.
+struct MassInst {
+    const void *c;
+    long long n;
+    int blk0, nblk;
+};
+constexpr int kMassThreads = 256;
+hipError_t launch_ch_mass(int state_dtype, const MassInst *inst, int ninst, int blocks,
+                          double *partial, double *out, hipStream_t s);
+
+}  // namespace mxs

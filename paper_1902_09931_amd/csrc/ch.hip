@@ -1,0 +1,267 @@
+// Kernels of the ADI Cahn-Hilliard step (Sec. 5.1) other than the line
+// solves: the fused right-hand side of the x sweep, and the mass reduction.
+//
+// The right-hand side streams the rows of C^n and C^{n-1} once: every input
+// row is turned into Cbar = 2 C^n - C^{n-1} and f = C^n^3 - C^n (staged in LDS
+// with a two-column periodic halo), then multiplied into the five pending
+// output rows it meets (5x5 biharmonic window on Cbar, 3x3 Laplacian window
+// on f), and the centre row adds -2/3 (C^n - C^{n-1}).  One read of each
+// state element and one write of R per point, as for the stencils.
+#include "ch.h"
+
+namespace mxs {
+
+namespace {
+
+template <typename A> __device__ __forceinline__ A wb_of(const RhsInst &I, int k);
+template <> __device__ __forceinline__ double wb_of<double>(const RhsInst &I, int k) { return I.wb[k]; }
+template <> __device__ __forceinline__ float wb_of<float>(const RhsInst &I, int k) { return I.wbf[k]; }
+template <typename A> __device__ __forceinline__ A wl_of(const RhsInst &I, int k);
+template <> __device__ __forceinline__ double wl_of<double>(const RhsInst &I, int k) { return I.wl[k]; }
+template <> __device__ __forceinline__ float wl_of<float>(const RhsInst &I, int k) { return I.wlf[k]; }
+template <typename A> __device__ __forceinline__ A cd_of(const RhsInst &I);
+template <> __device__ __forceinline__ double cd_of<double>(const RhsInst &I) { return I.cdiff; }
+template <> __device__ __forceinline__ float cd_of<float>(const RhsInst &I) { return I.cdifff; }
+
+template <typename T, typename TW>
+__global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__restrict__ inst,
+                                                             int ninst) {
+    using A = typename St<T>::acc;
+    constexpr int V = St<T>::V;
+    constexpr int PAD = V >= 2 ? V : 2;   // two halo columns, rounded up to a vector
+    constexpr int G = 4;
+    constexpr int XB = V + 4;             // biharmonic window per thread
+    constexpr int XL = V + 2;             // Laplacian window per thread
+
+    int g = 0;
+    while (g + 1 < ninst && inst[g + 1].blk0 <= static_cast<int>(blockIdx.x)) ++g;
+    const RhsInst &I = inst[g];
+    const int nt = kRhsThreads;
+    const int t = threadIdx.x;
+    const int W = nt * V;
+    const int rowlen = PAD + W + PAD;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    A *lcb = reinterpret_cast<A *>(smem_raw);
+    A *lfc = lcb + G * rowlen;
+
+    const int local = blockIdx.x - I.blk0;
+    const int tile = xcd_tile(local, I.nstrips * I.nchunks);
+    const int strip = tile / I.nchunks;
+    const int chunk = tile - strip * I.nchunks;
+    const int i0 = strip * W;
+    const int j0 = chunk * I.rows;
+    const int H = min(I.rows, I.ny - j0);
+    const int niter = H + 4;
+    const int ib = i0 + t * V;
+    const int nx = I.nx, ny = I.ny;
+    const bool full_vec = ((nx % V) == 0) && (ib + V <= nx);
+    const T *cur = static_cast<const T *>(I.cur);
+    const T *prev = static_cast<const T *>(I.prev);
+    TW *R = static_cast<TW *>(I.R);
+    const A cdiff = cd_of<A>(I);
+
+    A acc[5][V];
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[k][v] = A(0);
+
+    for (int s0 = 0; s0 < niter; s0 += G) {
+        A cb[G][V], fc[G][V], df[G][V];
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int r = static_cast<int>(wrap_ll(j0 - 2 + s0 + u, ny));
+            const T *cr = cur + static_cast<long long>(r) * nx;
+            const T *pr = prev + static_cast<long long>(r) * nx;
+            A c[V], p[V];
+            if (full_vec) {
+                load_vec<T>(cr + ib, c);
+                load_vec<T>(pr + ib, p);
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const int col = static_cast<int>(wrap_ll(ib + v, nx));
+                    c[v] = to_acc<T>(cr[col]);
+                    p[v] = to_acc<T>(pr[col]);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                cb[u][v] = A(2) * c[v] - p[v];
+                fc[u][v] = c[v] * c[v] * c[v] - c[v];
+                df[u][v] = c[v] - p[v];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                lcb[u * rowlen + PAD + t * V + v] = cb[u][v];
+                lfc[u * rowlen + PAD + t * V + v] = fc[u][v];
+            }
+        for (int h = t; h < G * 2 * PAD; h += nt) {
+            const int u = h / (2 * PAD);
+            const int hh = h - u * 2 * PAD;
+            const int r = static_cast<int>(wrap_ll(j0 - 2 + s0 + u, ny));
+            const long long col = hh < PAD ? static_cast<long long>(i0) - PAD + hh
+                                           : static_cast<long long>(i0) + W + (hh - PAD);
+            const int cc = static_cast<int>(wrap_ll(col, nx));
+            const A c = to_acc<T>(cur[static_cast<long long>(r) * nx + cc]);
+            const A p = to_acc<T>(prev[static_cast<long long>(r) * nx + cc]);
+            const int pos = u * rowlen + (hh < PAD ? hh : W + hh);
+            lcb[pos] = A(2) * c - p;
+            lfc[pos] = c * c * c - c;
+        }
+        __syncthreads();
+
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int s = s0 + u;
+            if (s < niter) {
+                A x[XB], y[XL];
+                const A *bp = lcb + u * rowlen + PAD + t * V - 2;
+                const A *fp = lfc + u * rowlen + PAD + t * V - 1;
+#pragma unroll
+                for (int q = 0; q < XB; ++q) x[q] = bp[q];
+#pragma unroll
+                for (int q = 0; q < XL; ++q) y[q] = fp[q];
+                // acc[k] is output row s - 4 + k, met by window row 4 - k
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+#pragma unroll
+                    for (int p = 0; p < 5; ++p) {
+                        const A w = wb_of<A>(I, (4 - k) * 5 + p);
+                        if (w != A(0)) {
+#pragma unroll
+                            for (int v = 0; v < V; ++v) acc[k][v] = fma(w, x[v + p], acc[k][v]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 1; k <= 3; ++k) {
+#pragma unroll
+                    for (int p = 0; p < 3; ++p) {
+                        const A w = wl_of<A>(I, (3 - k) * 3 + p);
+                        if (w != A(0)) {
+#pragma unroll
+                            for (int v = 0; v < V; ++v) acc[k][v] = fma(w, y[v + p], acc[k][v]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[2][v] = fma(cdiff, df[u][v], acc[2][v]);
+
+                const int jj = s - 4;
+                if (jj >= 0 && jj < H) {
+                    TW *rowp = R + static_cast<long long>(j0 + jj) * nx;
+                    if (full_vec) {
+                        store_vec<TW>(rowp + ib, acc[0]);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < V; ++v)
+                            if (ib + v < nx) rowp[ib + v] = from_acc<TW>(acc[0][v]);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) acc[k][v] = acc[k + 1][v];
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[4][v] = A(0);
+            }
+        }
+    }
+}
+
+// ---- mass ------------------------------------------------------------------------
+
+template <typename T> __device__ __forceinline__ double elem_f64(const T *p, long long i);
+template <> __device__ __forceinline__ double elem_f64<double>(const double *p, long long i) { return p[i]; }
+template <> __device__ __forceinline__ double elem_f64<float>(const float *p, long long i) { return p[i]; }
+template <> __device__ __forceinline__ double elem_f64<bf16>(const bf16 *p, long long i) {
+    return bf16_to_float(p[i].bits);
+}
+
+__device__ double block_sum(double v, double *red) {
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int h = kMassThreads / 2; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMassThreads) mass_partial_kernel(const MassInst *__restrict__ inst,
+                                                                   int ninst, double *partial) {
+    __shared__ double red[kMassThreads];
+    int g = 0;
+    while (g + 1 < ninst && inst[g + 1].blk0 <= static_cast<int>(blockIdx.x)) ++g;
+    const MassInst &I = inst[g];
+    const long long local = blockIdx.x - I.blk0;
+    const long long chunk = (I.n + I.nblk - 1) / I.nblk;
+    const long long a = local * chunk;
+    const long long b = min(I.n, a + chunk);
+    const T *c = static_cast<const T *>(I.c);
+    double s = 0.0;
+    for (long long i = a + threadIdx.x; i < b; i += kMassThreads) s += elem_f64<T>(c, i);
+    const double tot = block_sum(s, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kMassThreads) mass_final_kernel(const MassInst *__restrict__ inst,
+                                                                 const double *partial, double *out) {
+    __shared__ double red[kMassThreads];
+    const MassInst &I = inst[blockIdx.x];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < I.nblk; i += kMassThreads) s += partial[I.blk0 + i];
+    const double tot = block_sum(s, red);
+    if (threadIdx.x == 0) out[blockIdx.x] = tot;
+}
+
+template <typename T, typename TW>
+hipError_t rhs_one(const RhsInst *inst, int ninst, int blocks, hipStream_t s) {
+    using A = typename St<T>::acc;
+    constexpr int V = St<T>::V;
+    constexpr int PAD = V >= 2 ? V : 2;
+    const size_t lds = 2 * 4 * static_cast<size_t>(PAD + kRhsThreads * V + PAD) * sizeof(A);
+    hipLaunchKernelGGL((ch_rhs_kernel<T, TW>), dim3(blocks), dim3(kRhsThreads), lds, s, inst, ninst);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mass_one(const MassInst *inst, int ninst, int blocks, double *partial, double *out,
+                    hipStream_t s) {
+    hipLaunchKernelGGL((mass_partial_kernel<T>), dim3(blocks), dim3(kMassThreads), 0, s, inst, ninst,
+                       partial);
+    hipLaunchKernelGGL(mass_final_kernel, dim3(ninst), dim3(kMassThreads), 0, s, inst, partial, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_ch_rhs(int state_dtype, const RhsInst *inst, int ninst, int blocks, hipStream_t s) {
+    switch (state_dtype) {
+    case F64: return rhs_one<double, double>(inst, ninst, blocks, s);
+    case F32: return rhs_one<float, float>(inst, ninst, blocks, s);
+    case BF16: return rhs_one<bf16, float>(inst, ninst, blocks, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_ch_mass(int state_dtype, const MassInst *inst, int ninst, int blocks,
+                          double *partial, double *out, hipStream_t s) {
+    switch (state_dtype) {
+    case F64: return mass_one<double>(inst, ninst, blocks, partial, out, s);
+    case F32: return mass_one<float>(inst, ninst, blocks, partial, out, s);
+    case BF16: return mass_one<bf16>(inst, ninst, blocks, partial, out, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mxs

@@ -1,0 +1,412 @@
+// Plans for the ADI Cahn-Hilliard step on one grid or an ensemble of grids
+// (Sec. 5.1): mxs_ch_create, mxs_ch_ensemble_create, mxs_ch_step and friends.
+//
+// One step is five launches, each covering every instance of the plan:
+//   1. right-hand side R from (C^{n-1}, C^n)                   (ch.hip)
+//   2. L_x w = R on every row, in place                        (cyclic.hip)
+//   3-5. L_y v = w on every column, three phases, the last one
+//        writing C^{n+1} = 2 C^n - C^{n-1} + v                  (cyclic.hip)
+// The three state buffers rotate, so the kernel arguments differ between
+// consecutive steps; the plan keeps one instance table (and one captured
+// HIP graph) per rotation.
+#include "ch.h"
+#include "plans.h"
+#include "solve.h"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+namespace mxs {
+
+int wave_grid(long long nlines, size_t lds_bytes);
+
+namespace {
+
+struct Inst {
+    int nx, ny;
+    double dx, dy, dt;
+    void *buf[3];     // caller's buffers in the initial roles prev, cur, next
+    DevBuf w, carry;  // plan-owned
+};
+
+// The 5x5 biharmonic window d_xxxx + 2 d_xxyy + d_yyyy from the second-order
+// central differences (Sec. 5.1) and the cross stencil of Fig. 1.
+void biharmonic_window(double dx, double dy, double *w) {
+    const double d4[5] = {1.0, -4.0, 6.0, -4.0, 1.0};
+    const double d2[3] = {1.0, -2.0, 1.0};
+    for (int k = 0; k < 25; ++k) w[k] = 0.0;
+    const double hx = 1.0 / (dx * dx * dx * dx), hy = 1.0 / (dy * dy * dy * dy);
+    const double hxy = 1.0 / (dx * dx * dy * dy);
+    for (int k = 0; k < 5; ++k) {
+        w[2 * 5 + k] += d4[k] * hx;
+        w[k * 5 + 2] += d4[k] * hy;
+    }
+    for (int b = 0; b < 3; ++b)
+        for (int a = 0; a < 3; ++a) w[(b + 1) * 5 + (a + 1)] += 2.0 * d2[b] * d2[a] * hxy;
+}
+
+// The 3x3 window of the 5-point Laplacian.
+void laplacian_window(double dx, double dy, double *w) {
+    const double d2[3] = {1.0, -2.0, 1.0};
+    for (int k = 0; k < 9; ++k) w[k] = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        w[1 * 3 + k] += d2[k] / (dx * dx);
+        w[k * 3 + 1] += d2[k] / (dy * dy);
+    }
+}
+
+bool aligned16(const void *p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; }
+
+struct CHPlan final : mxs_plan_s {
+    int dtype = F64, wdtype = F64;
+    double D = 1, gamma = 0.01;
+    std::vector<Inst> inst;
+    long long steps = 0;
+
+    std::vector<RhsInst> rhs_h[3];
+    std::vector<RowsInst> rows_h;
+    std::vector<ColsInst> cols_h[3];
+    std::vector<MassInst> mass_h[3];
+    DevBuf rhs_d[3], rows_d, cols_d[3], mass_d[3];
+    DevBuf partial, mass_out;
+    double *mass_host = nullptr;
+    int rhs_blocks = 0, row_lines = 0, row_grid = 1, colsAC = 0, colsB = 0, mass_blocks = 0;
+    size_t row_lds = 0;
+
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+
+    CHPlan() : mxs_plan_s(KIND_CH) {}
+    ~CHPlan() override {
+        for (auto &e : exec)
+            if (e) (void)hipGraphExecDestroy(e);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (mass_host) (void)hipHostFree(mass_host);
+    }
+
+    int ninst() const { return static_cast<int>(inst.size()); }
+
+    hipError_t enqueue(int r, hipStream_t s) {
+        hipError_t e = launch_ch_rhs(dtype, static_cast<const RhsInst *>(rhs_d[r].ptr), ninst(),
+                                     rhs_blocks, s);
+        if (e != hipSuccess) return e;
+        e = launch_rows(wdtype, 2, static_cast<const RowsInst *>(rows_d.ptr), ninst(), row_lines,
+                        row_grid, row_lds, s);
+        if (e != hipSuccess) return e;
+        return launch_cols(wdtype, dtype, 2, 1, static_cast<const ColsInst *>(cols_d[r].ptr),
+                           ninst(), colsAC, colsB, s);
+    }
+
+    hipError_t capture(int r) {
+        if (!cap) {
+            hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        hipError_t le = enqueue(r, cap);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cap, &graph);
+        if (le != hipSuccess) e = le;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec[r], graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        return e;
+    }
+
+    mxs_status step(int nsteps, bool use_graph, hipStream_t s) {
+        for (int k = 0; k < nsteps; ++k) {
+            const int r = static_cast<int>(steps % 3);
+            hipError_t e;
+            if (use_graph) {
+                if (!exec[r]) {
+                    e = capture(r);
+                    if (e != hipSuccess) return hip_fail(e, "graph capture of the step");
+                }
+                e = hipGraphLaunch(exec[r], s);
+            } else {
+                e = enqueue(r, s);
+            }
+            if (e != hipSuccess) return hip_fail(e, "step launch");
+            ++steps;
+        }
+        return MXS_OK;
+    }
+
+    mxs_status mass(double *out, hipStream_t s) {
+        const int r = static_cast<int>(steps % 3);
+        hipError_t e = launch_ch_mass(dtype, static_cast<const MassInst *>(mass_d[r].ptr), ninst(),
+                                      mass_blocks, static_cast<double *>(partial.ptr),
+                                      static_cast<double *>(mass_out.ptr), s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(mass_host, mass_out.ptr, sizeof(double) * ninst(),
+                               hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "mass reduction");
+        bool finite = true;
+        for (int g = 0; g < ninst(); ++g) {
+            out[g] = mass_host[g];
+            finite = finite && std::isfinite(mass_host[g]);
+        }
+        return finite ? MXS_OK : fail(MXS_ERR_NONFINITE, "the mass is not finite");
+    }
+
+    mxs_status build() {
+        const int n = ninst();
+        const int cus = device_cu_count();
+        const int Vs = dtype == F64 ? 2 : 4;
+        // right-hand side tables
+        int blk = 0, maxnx = 0;
+        long long total_tiles = 0;
+        for (const Inst &I : inst) total_tiles += (I.nx + kRhsThreads * Vs - 1) / (kRhsThreads * Vs) * ((I.ny + 63) / 64);
+        int rows = 64;
+        while (rows > 8 && total_tiles < 8LL * cus) {
+            rows /= 2;
+            total_tiles = 0;
+            for (const Inst &I : inst) total_tiles += (I.nx + kRhsThreads * Vs - 1) / (kRhsThreads * Vs) * ((I.ny + rows - 1) / rows);
+        }
+        for (int r = 0; r < 3; ++r) rhs_h[r].resize(n);
+        for (int g = 0; g < n; ++g) {
+            const Inst &I = inst[g];
+            RhsInst ri{};
+            ri.nx = I.nx;
+            ri.ny = I.ny;
+            ri.nstrips = (I.nx + kRhsThreads * Vs - 1) / (kRhsThreads * Vs);
+            ri.rows = rows;
+            ri.nchunks = (I.ny + rows - 1) / rows;
+            ri.blk0 = blk;
+            blk += ri.nstrips * ri.nchunks;
+            const double a = 2.0 / 3.0 * D * gamma * I.dt;
+            double wb[25], wl[9];
+            biharmonic_window(I.dx, I.dy, wb);
+            laplacian_window(I.dx, I.dy, wl);
+            for (int k = 0; k < 25; ++k) {
+                ri.wb[k] = -a * wb[k];
+                ri.wbf[k] = static_cast<float>(ri.wb[k]);
+            }
+            for (int k = 0; k < 9; ++k) {
+                ri.wl[k] = 2.0 / 3.0 * D * I.dt * wl[k];
+                ri.wlf[k] = static_cast<float>(ri.wl[k]);
+            }
+            ri.cdiff = -2.0 / 3.0;
+            ri.cdifff = static_cast<float>(ri.cdiff);
+            ri.R = I.w.ptr;
+            for (int r = 0; r < 3; ++r) {
+                RhsInst rr = ri;
+                rr.prev = I.buf[r % 3];
+                rr.cur = I.buf[(r + 1) % 3];
+                rhs_h[r][g] = rr;
+            }
+            maxnx = std::max(maxnx, I.nx);
+        }
+        rhs_blocks = blk;
+
+        // row solves (in place on w) and column solves (w -> C^{n+1})
+        rows_h.resize(n);
+        for (int r = 0; r < 3; ++r) cols_h[r].resize(n);
+        int line = 0, bAC = 0, bB = 0;
+        for (int g = 0; g < n; ++g) {
+            Inst &I = inst[g];
+            const double a = 2.0 / 3.0 * D * gamma * I.dt;
+            const double bx = a / (I.dx * I.dx * I.dx * I.dx), by = a / (I.dy * I.dy * I.dy * I.dy);
+            const double cx[3] = {1.0 + 6.0 * bx, -4.0 * bx, bx};
+            const double cyv[3] = {1.0 + 6.0 * by, -4.0 * by, by};
+            CyclicFactor fx, fy;
+            if (factor_symmetric_circulant(2, cx, &fx) || factor_symmetric_circulant(2, cyv, &fy))
+                return fail(MXS_ERR_INVALID_ARG, "could not factor the ADI line operators");
+            RowsInst ro{};
+            ro.in = I.w.ptr;
+            ro.out = I.w.ptr;
+            ro.ld = I.nx;
+            ro.nx = I.nx;
+            ro.ny = I.ny;
+            ro.line0 = line;
+            ro.p1 = fx.p1;
+            ro.p2 = fx.p2;
+            ro.invK = fx.invK;
+            rows_h[g] = ro;
+            line += I.ny;
+
+            ColsInst co{};
+            fill_cols_coef(fy, 2, I.ny, &co);
+            co.ld = I.nx;
+            co.nx = I.nx;
+            co.ny = I.ny;
+            co.nstrips = (I.nx + kColsThreads - 1) / kColsThreads;
+            co.blk0 = bAC;
+            co.blkB0 = bB;
+            bAC += co.nstrips * co.nseg;
+            bB += co.nstrips;
+            hipError_t e = I.carry.alloc(sizeof(double) * 4 * static_cast<size_t>(I.nx) * co.nseg);
+            if (e != hipSuccess) return hip_fail(e, "carry allocation");
+            co.carry = static_cast<double *>(I.carry.ptr);
+            co.rhs = I.w.ptr;
+            for (int r = 0; r < 3; ++r) {
+                ColsInst cc = co;
+                cc.prev = I.buf[r % 3];
+                cc.cur = I.buf[(r + 1) % 3];
+                cc.x = I.buf[(r + 2) % 3];
+                cols_h[r][g] = cc;
+            }
+        }
+        row_lines = line;
+        colsAC = bAC;
+        colsB = bB;
+        row_lds = wave_line_lds_bytes(wave_chunk(maxnx));
+        if (row_lds > static_cast<size_t>(device_lds_limit()))
+            return fail(MXS_ERR_UNSUPPORTED, "rows too long for the LDS of one workgroup");
+        row_grid = wave_grid(row_lines, row_lds);
+
+        // mass
+        int mb = 0;
+        for (int r = 0; r < 3; ++r) mass_h[r].resize(n);
+        for (int g = 0; g < n; ++g) {
+            const long long npts = static_cast<long long>(inst[g].nx) * inst[g].ny;
+            const int nblk = static_cast<int>(std::min<long long>(256, (npts + 65535) / 65536));
+            for (int r = 0; r < 3; ++r) {
+                MassInst m{};
+                m.c = inst[g].buf[(r + 1) % 3];
+                m.n = npts;
+                m.blk0 = mb;
+                m.nblk = nblk;
+                mass_h[r][g] = m;
+            }
+            mb += nblk;
+        }
+        mass_blocks = mb;
+
+        hipError_t e = hipSuccess;
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+            e = rhs_d[r].upload(rhs_h[r].data(), sizeof(RhsInst) * n);
+            if (e == hipSuccess) e = cols_d[r].upload(cols_h[r].data(), sizeof(ColsInst) * n);
+            if (e == hipSuccess) e = mass_d[r].upload(mass_h[r].data(), sizeof(MassInst) * n);
+        }
+        if (e == hipSuccess) e = rows_d.upload(rows_h.data(), sizeof(RowsInst) * n);
+        if (e == hipSuccess) e = partial.alloc(sizeof(double) * mass_blocks);
+        if (e == hipSuccess) e = mass_out.alloc(sizeof(double) * n);
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&mass_host), sizeof(double) * n, 0);
+        if (e != hipSuccess) return hip_fail(e, "plan tables upload");
+        return MXS_OK;
+    }
+};
+
+mxs_status create_ch(int count, const int *nx, const int *ny, const double *dx, const double *dy,
+                     const double *dt, double D, double gamma, int dtype, void *const *c_prev,
+                     void *const *c_cur, void *const *c_next, mxs_plan *plan) {
+    if (!plan) return fail(MXS_ERR_INVALID_ARG, "plan output pointer is NULL");
+    *plan = nullptr;
+    if (count <= 0 || !nx || !ny || !dx || !dy || !dt || !c_prev || !c_cur || !c_next)
+        return fail(MXS_ERR_INVALID_ARG, "missing arguments");
+    if (!valid_dtype(dtype)) return fail(MXS_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+    if (!(D > 0) || !(gamma > 0) || !std::isfinite(D) || !std::isfinite(gamma))
+        return fail(MXS_ERR_INVALID_ARG, "need D > 0 and gamma > 0");
+    CHPlan *p = new (std::nothrow) CHPlan();
+    if (!p) return fail(MXS_ERR_OOM, "host allocation failed");
+    p->dtype = dtype;
+    p->wdtype = dtype == F64 ? F64 : F32;
+    p->D = D;
+    p->gamma = gamma;
+    p->inst.resize(count);
+    for (int g = 0; g < count; ++g) {
+        Inst &I = p->inst[g];
+        if (nx[g] < 8 || ny[g] < 8 || nx[g] > 16384 || ny[g] > 16384 || !(dx[g] > 0) ||
+            !(dy[g] > 0) || !(dt[g] > 0) || !std::isfinite(dx[g]) || !std::isfinite(dy[g]) ||
+            !std::isfinite(dt[g])) {
+            delete p;
+            return fail(MXS_ERR_INVALID_ARG, "instance %d: need 8 <= nx, ny <= 16384 and positive dx, dy, dt", g);
+        }
+        I.nx = nx[g];
+        I.ny = ny[g];
+        I.dx = dx[g];
+        I.dy = dy[g];
+        I.dt = dt[g];
+        I.buf[0] = c_prev[g];
+        I.buf[1] = c_cur[g];
+        I.buf[2] = c_next[g];
+        const size_t bytes = static_cast<size_t>(I.nx) * I.ny * dtype_size(dtype);
+        for (int q = 0; q < 3; ++q) {
+            if (!I.buf[q] || !aligned16(I.buf[q])) {
+                delete p;
+                return fail(I.buf[q] ? MXS_ERR_UNSUPPORTED : MXS_ERR_INVALID_ARG,
+                            "instance %d: state buffers must be non-NULL and 16-byte aligned", g);
+            }
+            for (int r = 0; r < q; ++r)
+                if (ranges_overlap(I.buf[q], bytes, I.buf[r], bytes)) {
+                    delete p;
+                    return fail(MXS_ERR_ALIAS, "instance %d: state buffers overlap", g);
+                }
+        }
+        hipError_t e = I.w.alloc(static_cast<size_t>(I.nx) * I.ny * dtype_size(p->wdtype));
+        if (e != hipSuccess) {
+            delete p;
+            return hip_fail(e, "scratch allocation");
+        }
+    }
+    mxs_status st = p->build();
+    if (st) {
+        delete p;
+        return st;
+    }
+    register_plan(p);
+    *plan = p;
+    return MXS_OK;
+}
+
+CHPlan *as_ch(mxs_plan plan) {
+    if (!plan || !is_live(plan) || plan->kind != KIND_CH) return nullptr;
+    return static_cast<CHPlan *>(plan);
+}
+
+}  // namespace
+}  // namespace mxs
+
+using namespace mxs;
+
+extern "C" {
+
+mxs_status mxs_ch_create(int nx, int ny, double dx, double dy, double dt, double D, double gamma,
+                         int dtype, void *c_prev, void *c_cur, void *c_next, mxs_plan *plan) {
+    void *p[1] = {c_prev}, *c[1] = {c_cur}, *n[1] = {c_next};
+    return create_ch(1, &nx, &ny, &dx, &dy, &dt, D, gamma, dtype, p, c, n, plan);
+}
+
+mxs_status mxs_ch_ensemble_create(int count, const int *nx, const int *ny, const double *dx,
+                                  const double *dy, const double *dt, double D, double gamma,
+                                  int dtype, void *const *c_prev, void *const *c_cur,
+                                  void *const *c_next, mxs_plan *plan) {
+    return create_ch(count, nx, ny, dx, dy, dt, D, gamma, dtype, c_prev, c_cur, c_next, plan);
+}
+
+mxs_status mxs_ch_step(mxs_plan plan, int nsteps, int use_graph, void *hip_stream) {
+    CHPlan *p = as_ch(plan);
+    if (!p) return fail(MXS_ERR_BAD_HANDLE, "not a Cahn-Hilliard plan");
+    if (nsteps < 0) return fail(MXS_ERR_INVALID_ARG, "nsteps < 0");
+    return p->step(nsteps, use_graph != 0, static_cast<hipStream_t>(hip_stream));
+}
+
+mxs_status mxs_ch_state(mxs_plan plan, int k, void **c_prev, void **c_cur) {
+    CHPlan *p = as_ch(plan);
+    if (!p) return fail(MXS_ERR_BAD_HANDLE, "not a Cahn-Hilliard plan");
+    if (k < 0 || k >= p->ninst()) return fail(MXS_ERR_INVALID_ARG, "instance %d out of range", k);
+    const int r = static_cast<int>(p->steps % 3);
+    if (c_prev) *c_prev = p->inst[k].buf[r % 3];
+    if (c_cur) *c_cur = p->inst[k].buf[(r + 1) % 3];
+    return MXS_OK;
+}
+
+mxs_status mxs_ch_steps_taken(mxs_plan plan, long long *nsteps) {
+    CHPlan *p = as_ch(plan);
+    if (!p) return fail(MXS_ERR_BAD_HANDLE, "not a Cahn-Hilliard plan");
+    if (!nsteps) return fail(MXS_ERR_INVALID_ARG, "nsteps is NULL");
+    *nsteps = p->steps;
+    return MXS_OK;
+}
+
+mxs_status mxs_ch_mass(mxs_plan plan, double *host_out, void *hip_stream) {
+    CHPlan *p = as_ch(plan);
+    if (!p) return fail(MXS_ERR_BAD_HANDLE, "not a Cahn-Hilliard plan");
+    if (!host_out) return fail(MXS_ERR_INVALID_ARG, "host_out is NULL");
+    return p->mass(host_out, static_cast<hipStream_t>(hip_stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,454 @@
+// Cyclic banded line solves (the periodic line inversions of the ADI scheme,
+// Sec. 5.1) on the GPU, from the factorisation A = K P(S) P(S^-1) described
+// in solve.h.  All elimination arithmetic is double.
+//
+// Contiguous lines (rows of a grid, or uneven lines stored back to back) go
+// one line per wavefront.  The line is copied into LDS; lane l owns the k
+// consecutive elements of chunk l.  Each cyclic recurrence is then
+//   1. a local pass: every lane runs the recurrence over its chunk from a
+//      zero state, giving the affine map state_out = M^len state_in + e;
+//   2. an inclusive scan of these affine maps across the 64 lanes with
+//      cross-lane shuffles, whose total gives the wrap-around closure
+//      state_-1 = (I - M^n)^-1 e_total;
+//   3. a final pass from each lane's true incoming state.
+// The backward recurrence is the same with the index order reversed.
+//
+// Columns of a grid go in three phases over segments of kSeg rows, one lane
+// per column (coalesced row accesses):
+//   A. per segment: the forward recurrence from zero (end state e) and the
+//      backward recurrence from zero over that output (top state g);
+//   B. per column: scans over the segments give every segment's true
+//      forward incoming state c_s and backward incoming state d_s;
+//   C. per segment: both recurrences again from (c_s, d_s), then the output
+//      (optionally fused with the Cahn-Hilliard update C^{n+1} = Cbar + v).
+#include "solve.h"
+
+namespace mxs {
+
+namespace {
+
+template <typename T> __device__ __forceinline__ double to_f64(T v);
+template <> __device__ __forceinline__ double to_f64<double>(double v) { return v; }
+template <> __device__ __forceinline__ double to_f64<float>(float v) { return static_cast<double>(v); }
+template <> __device__ __forceinline__ double to_f64<bf16>(bf16 v) {
+    return static_cast<double>(bf16_to_float(v.bits));
+}
+template <typename T> __device__ __forceinline__ T from_f64(double v);
+template <> __device__ __forceinline__ double from_f64<double>(double v) { return v; }
+template <> __device__ __forceinline__ float from_f64<float>(double v) { return static_cast<float>(v); }
+// double -> bf16 rounds once, to nearest even, via the exact float split:
+// the float nearest to v can round the wrong way only at a bf16 tie; the
+// remainder v - float(v) decides that case.
+template <> __device__ __forceinline__ bf16 from_f64<bf16>(double v) {
+    const float f = static_cast<float>(v);
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return bf16{float_to_bf16(f)};
+    const double rem = v - static_cast<double>(f);
+    if ((u & 0xffffu) == 0x8000u && rem != 0.0) {
+        // exactly halfway in float but not in double: round by the remainder
+        const bool up = (rem > 0) == ((u & 0x80000000u) == 0);
+        return bf16{static_cast<uint16_t>((u >> 16) + (up ? 1u : 0u))};
+    }
+    return bf16{float_to_bf16(f)};
+}
+
+// ---- affine maps on the 2-vector state (y_i, y_{i-1}) ----------------------
+struct Aff {
+    double a, b, c, d;   // matrix, row-major
+    double e0, e1;       // offset
+};
+
+__device__ __forceinline__ Aff compose(const Aff &hi, const Aff &lo) {
+    // (hi o lo)(s) = hi.T (lo.T s + lo.e) + hi.e
+    Aff r;
+    r.a = hi.a * lo.a + hi.b * lo.c;
+    r.b = hi.a * lo.b + hi.b * lo.d;
+    r.c = hi.c * lo.a + hi.d * lo.c;
+    r.d = hi.c * lo.b + hi.d * lo.d;
+    r.e0 = hi.a * lo.e0 + hi.b * lo.e1 + hi.e0;
+    r.e1 = hi.c * lo.e0 + hi.d * lo.e1 + hi.e1;
+    return r;
+}
+
+template <bool UP> __device__ __forceinline__ double shfl_step(double v, int d) {
+    return UP ? __shfl_up(v, d, 64) : __shfl_down(v, d, 64);
+}
+
+template <bool UP> __device__ __forceinline__ Aff shfl_aff(const Aff &x, int d) {
+    Aff r;
+    r.a = shfl_step<UP>(x.a, d);
+    r.b = shfl_step<UP>(x.b, d);
+    r.c = shfl_step<UP>(x.c, d);
+    r.d = shfl_step<UP>(x.d, d);
+    r.e0 = shfl_step<UP>(x.e0, d);
+    r.e1 = shfl_step<UP>(x.e1, d);
+    return r;
+}
+
+__device__ __forceinline__ Aff bcast_aff(const Aff &x, int lane) {
+    Aff r;
+    r.a = __shfl(x.a, lane, 64);
+    r.b = __shfl(x.b, lane, 64);
+    r.c = __shfl(x.c, lane, 64);
+    r.d = __shfl(x.d, lane, 64);
+    r.e0 = __shfl(x.e0, lane, 64);
+    r.e1 = __shfl(x.e1, lane, 64);
+    return r;
+}
+
+// M^len for the companion matrix M = [[p1, p2], [1, 0]].
+__device__ __forceinline__ void companion_pow(double p1, double p2, int len, Aff &m) {
+    double ra = 1, rb = 0, rc = 0, rd = 1;
+    double ba = p1, bb = p2, bc = 1, bd = 0;
+    while (len) {
+        if (len & 1) {
+            const double na = ra * ba + rb * bc, nb = ra * bb + rb * bd;
+            const double nc = rc * ba + rd * bc, nd = rc * bb + rd * bd;
+            ra = na; rb = nb; rc = nc; rd = nd;
+        }
+        const double na = ba * ba + bb * bc, nb = ba * bb + bb * bd;
+        const double nc = bc * ba + bd * bc, nd = bc * bb + bd * bd;
+        ba = na; bb = nb; bc = nc; bd = nd;
+        len >>= 1;
+    }
+    m.a = ra; m.b = rb; m.c = rc; m.d = rd;
+}
+
+// One cyclic recurrence y_i = b_i + p1 y_{i-1} + p2 y_{i-2} over a line held in
+// LDS in place (REV: the index order reversed, i.e. the backward recurrence).
+template <int BW, bool REV>
+__device__ void wave_cyclic_pass(double *line, int n, int k, double p1, double p2) {
+    const int lane = threadIdx.x & 63;
+    const int start = min(lane * k, n);
+    const int len = min(start + k, n) - start;
+    double *base = line + lane * (k + 1);
+
+    double s0 = 0.0, s1 = 0.0;
+    for (int q = 0; q < len; ++q) {
+        const int j = REV ? len - 1 - q : q;
+        const double y = BW == 2 ? fma(p2, s1, fma(p1, s0, base[j])) : fma(p1, s0, base[j]);
+        s1 = s0;
+        s0 = y;
+    }
+    Aff m;
+    companion_pow(p1, BW == 2 ? p2 : 0.0, len, m);
+    m.e0 = s0;
+    m.e1 = s1;
+
+    // inclusive scan in processing order (lanes ascending, or descending for REV)
+    Aff inc = m;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const Aff o = shfl_aff<!REV>(inc, d);
+        if (REV ? lane + d < 64 : lane >= d) inc = compose(inc, o);
+    }
+    const Aff tot = bcast_aff(inc, REV ? 0 : 63);
+    // wrap-around closure: state before the first element = (I - T)^-1 e
+    const double ia = 1.0 - tot.a, ib = -tot.b, ic = -tot.c, id = 1.0 - tot.d;
+    const double det = ia * id - ib * ic;
+    const double x0 = (id * tot.e0 - ib * tot.e1) / det;
+    const double x1 = (ia * tot.e1 - ic * tot.e0) / det;
+    const Aff pre = shfl_aff<!REV>(inc, 1);
+    const bool first = REV ? lane == 63 : lane == 0;
+    s0 = first ? x0 : pre.a * x0 + pre.b * x1 + pre.e0;
+    s1 = first ? x1 : pre.c * x0 + pre.d * x1 + pre.e1;
+
+    for (int q = 0; q < len; ++q) {
+        const int j = REV ? len - 1 - q : q;
+        const double y = BW == 2 ? fma(p2, s1, fma(p1, s0, base[j])) : fma(p1, s0, base[j]);
+        base[j] = y;
+        s1 = s0;
+        s0 = y;
+    }
+}
+
+__device__ __forceinline__ int lds_pos(int i, int k, float kinv) {
+    int c = static_cast<int>(static_cast<float>(i) * kinv);
+    if (c * k > i) --c;
+    else if ((c + 1) * k <= i) ++c;
+    return c * (k + 1) + (i - c * k);
+}
+
+// Solve one contiguous line (in -> out, may alias) with the wavefront.
+template <typename TI, typename TO, int BW>
+__device__ void wave_solve_line(const TI *in, TO *out, int n, double p1, double p2, double invK,
+                                double *line) {
+    const int lane = threadIdx.x & 63;
+    const int k = static_cast<int>((n + 127) / 128 * 2 < 2 ? 2 : (n + 127) / 128 * 2);
+    const float kinv = 1.0f / static_cast<float>(k);
+    __syncthreads();
+    for (int i = lane; i < n; i += 64) line[lds_pos(i, k, kinv)] = to_f64<TI>(in[i]);
+    __syncthreads();
+    wave_cyclic_pass<BW, false>(line, n, k, p1, p2);
+    wave_cyclic_pass<BW, true>(line, n, k, p1, p2);
+    __syncthreads();
+    for (int i = lane; i < n; i += 64) out[i] = from_f64<TO>(line[lds_pos(i, k, kinv)] * invK);
+}
+
+template <typename T, int BW>
+__global__ void __launch_bounds__(64) ragged_lines_kernel(const RaggedLines a) {
+    extern __shared__ double line[];
+    const T *in = static_cast<const T *>(a.in);
+    T *out = static_cast<T *>(a.out);
+    for (int li = blockIdx.x; li < a.nlines; li += gridDim.x) {
+        const int b = a.order[li];
+        const long long base = a.offsets[b];
+        const int n = static_cast<int>(a.offsets[b + 1] - base);
+        wave_solve_line<T, T, BW>(in + base, out + base, n, a.p1, a.p2, a.invK, line);
+    }
+}
+
+template <typename T, int BW>
+__global__ void __launch_bounds__(64) rows_kernel(const RowsInst *__restrict__ inst, int ninst,
+                                                  int nlines) {
+    extern __shared__ double line[];
+    for (int li = blockIdx.x; li < nlines; li += gridDim.x) {
+        int g = 0;
+        while (g + 1 < ninst && inst[g + 1].line0 <= li) ++g;
+        const RowsInst &I = inst[g];
+        const long long j = li - I.line0;
+        const T *in = static_cast<const T *>(I.in) + j * I.ld;
+        T *out = static_cast<T *>(I.out) + j * I.ld;
+        wave_solve_line<T, T, BW>(in, out, I.nx, I.p1, I.p2, I.invK, line);
+    }
+}
+
+// ---- columns -------------------------------------------------------------------
+
+__device__ __forceinline__ int find_inst(const ColsInst *inst, int ninst, int blk, bool phaseB) {
+    int g = 0;
+    while (g + 1 < ninst && (phaseB ? inst[g + 1].blkB0 : inst[g + 1].blk0) <= blk) ++g;
+    return g;
+}
+
+template <typename TR, int BW>
+__global__ void __launch_bounds__(kColsThreads) cols_phase_a(const ColsInst *__restrict__ inst,
+                                                            int ninst) {
+    const int g = find_inst(inst, ninst, blockIdx.x, false);
+    const ColsInst &I = inst[g];
+    const int local = blockIdx.x - I.blk0;
+    const int seg = local / I.nstrips;
+    const int strip = local - seg * I.nstrips;
+    const int i = strip * kColsThreads + threadIdx.x;
+    if (i >= I.nx) return;
+    const int r0 = seg * kSeg;
+    const int len = min(kSeg, I.ny - r0);
+    const TR *rhs = static_cast<const TR *>(I.rhs) + static_cast<long long>(r0) * I.ld + i;
+    const double p1 = I.p1, p2 = I.p2;
+
+    double y[kSeg];
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j) {
+        if (j < len) {
+            const double b = to_f64<TR>(rhs[static_cast<long long>(j) * I.ld]);
+            const double v = BW == 2 ? fma(p2, s1, fma(p1, s0, b)) : fma(p1, s0, b);
+            y[j] = v;
+            s1 = s0;
+            s0 = v;
+        }
+    }
+    double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+    for (int j = kSeg - 1; j >= 0; --j) {
+        if (j < len) {
+            const double v = BW == 2 ? fma(p2, t1, fma(p1, t0, y[j])) : fma(p1, t0, y[j]);
+            t1 = t0;
+            t0 = v;
+        }
+    }
+    double *cy = I.carry + static_cast<long long>(seg) * 4 * I.nx + i;
+    cy[0] = s0;
+    cy[I.nx] = s1;
+    cy[2 * I.nx] = t0;
+    cy[3 * I.nx] = t1;
+}
+
+template <int BW>
+__global__ void __launch_bounds__(kColsThreads) cols_phase_b(const ColsInst *__restrict__ inst,
+                                                            int ninst) {
+    const int g = find_inst(inst, ninst, blockIdx.x, true);
+    const ColsInst &I = inst[g];
+    const int i = (blockIdx.x - I.blkB0) * kColsThreads + threadIdx.x;
+    if (i >= I.nx) return;
+    const long long nx = I.nx;
+    double *cy = I.carry + i;
+    const int ns = I.nseg;
+
+    // forward: the end state from zero, then the closure and every incoming state
+    double c0 = 0.0, c1 = 0.0;
+    for (int s = 0; s < ns; ++s) {
+        const double *T = s == ns - 1 ? I.Tl : I.Tf;
+        const double e0 = cy[s * 4 * nx], e1 = cy[s * 4 * nx + nx];
+        const double n0 = T[0] * c0 + T[1] * c1 + e0;
+        const double n1 = T[2] * c0 + T[3] * c1 + e1;
+        c0 = n0;
+        c1 = n1;
+    }
+    double x0 = I.Cinv[0] * c0 + I.Cinv[1] * c1;
+    double x1 = I.Cinv[2] * c0 + I.Cinv[3] * c1;
+    c0 = x0;
+    c1 = x1;
+    for (int s = 0; s < ns; ++s) {
+        const double *T = s == ns - 1 ? I.Tl : I.Tf;
+        const double e0 = cy[s * 4 * nx], e1 = cy[s * 4 * nx + nx];
+        cy[s * 4 * nx] = c0;
+        cy[s * 4 * nx + nx] = c1;
+        const double n0 = T[0] * c0 + T[1] * c1 + e0;
+        const double n1 = T[2] * c0 + T[3] * c1 + e1;
+        c0 = n0;
+        c1 = n1;
+    }
+    // backward: top state t_s = g_s + Q_s c_s + N_s d_s, d_{s-1} = t_s (N = M)
+    double d0 = 0.0, d1 = 0.0;
+    for (int s = ns - 1; s >= 0; --s) {
+        const double *T = s == ns - 1 ? I.Tl : I.Tf;
+        const double *Q = s == ns - 1 ? I.Ql : I.Qf;
+        const double cs0 = cy[s * 4 * nx], cs1 = cy[s * 4 * nx + nx];
+        const double g0 = cy[s * 4 * nx + 2 * nx], g1 = cy[s * 4 * nx + 3 * nx];
+        const double n0 = g0 + Q[0] * cs0 + Q[1] * cs1 + T[0] * d0 + T[1] * d1;
+        const double n1 = g1 + Q[2] * cs0 + Q[3] * cs1 + T[2] * d0 + T[3] * d1;
+        d0 = n0;
+        d1 = n1;
+    }
+    x0 = I.Cinv[0] * d0 + I.Cinv[1] * d1;
+    x1 = I.Cinv[2] * d0 + I.Cinv[3] * d1;
+    d0 = x0;
+    d1 = x1;
+    for (int s = ns - 1; s >= 0; --s) {
+        const double *T = s == ns - 1 ? I.Tl : I.Tf;
+        const double *Q = s == ns - 1 ? I.Ql : I.Qf;
+        const double cs0 = cy[s * 4 * nx], cs1 = cy[s * 4 * nx + nx];
+        const double g0 = cy[s * 4 * nx + 2 * nx], g1 = cy[s * 4 * nx + 3 * nx];
+        cy[s * 4 * nx + 2 * nx] = d0;
+        cy[s * 4 * nx + 3 * nx] = d1;
+        const double n0 = g0 + Q[0] * cs0 + Q[1] * cs1 + T[0] * d0 + T[1] * d1;
+        const double n1 = g1 + Q[2] * cs0 + Q[3] * cs1 + T[2] * d0 + T[3] * d1;
+        d0 = n0;
+        d1 = n1;
+    }
+}
+
+template <typename TR, typename TX, int BW, int EPI>
+__global__ void __launch_bounds__(kColsThreads) cols_phase_c(const ColsInst *__restrict__ inst,
+                                                            int ninst) {
+    const int g = find_inst(inst, ninst, blockIdx.x, false);
+    const ColsInst &I = inst[g];
+    const int local = blockIdx.x - I.blk0;
+    const int seg = local / I.nstrips;
+    const int strip = local - seg * I.nstrips;
+    const int i = strip * kColsThreads + threadIdx.x;
+    if (i >= I.nx) return;
+    const int r0 = seg * kSeg;
+    const int len = min(kSeg, I.ny - r0);
+    const long long off = static_cast<long long>(r0) * I.ld + i;
+    const TR *rhs = static_cast<const TR *>(I.rhs) + off;
+    const double p1 = I.p1, p2 = I.p2;
+    const double *cy = I.carry + static_cast<long long>(seg) * 4 * I.nx + i;
+    double s0 = cy[0], s1 = cy[I.nx];
+    double t0 = cy[2 * I.nx], t1 = cy[3 * I.nx];
+
+    double y[kSeg];
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j) {
+        if (j < len) {
+            const double b = to_f64<TR>(rhs[static_cast<long long>(j) * I.ld]);
+            const double v = BW == 2 ? fma(p2, s1, fma(p1, s0, b)) : fma(p1, s0, b);
+            y[j] = v;
+            s1 = s0;
+            s0 = v;
+        }
+    }
+    TX *x = static_cast<TX *>(I.x) + off;
+    const TX *cur = static_cast<const TX *>(I.cur) + off;
+    const TX *prev = static_cast<const TX *>(I.prev) + off;
+#pragma unroll
+    for (int j = kSeg - 1; j >= 0; --j) {
+        if (j < len) {
+            const double v = BW == 2 ? fma(p2, t1, fma(p1, t0, y[j])) : fma(p1, t0, y[j]);
+            t1 = t0;
+            t0 = v;
+            const long long o = static_cast<long long>(j) * I.ld;
+            if (EPI == 1) {
+                const double cb = 2.0 * to_f64<TX>(cur[o]) - to_f64<TX>(prev[o]);
+                x[o] = from_f64<TX>(cb + v * I.invK);
+            } else {
+                x[o] = from_f64<TX>(v * I.invK);
+            }
+        }
+    }
+}
+
+template <typename T, int BW>
+hipError_t ragged_one(const RaggedLines &a, int grid, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((ragged_lines_kernel<T, BW>), dim3(grid), dim3(64), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int BW>
+hipError_t rows_one(const RowsInst *inst, int ninst, int nlines, int grid, size_t lds,
+                    hipStream_t s) {
+    hipLaunchKernelGGL((rows_kernel<T, BW>), dim3(grid), dim3(64), lds, s, inst, ninst, nlines);
+    return hipGetLastError();
+}
+
+template <typename TR, typename TX, int BW, int EPI>
+hipError_t cols_one(const ColsInst *inst, int ninst, int blocksAC, int blocksB, hipStream_t s) {
+    hipLaunchKernelGGL((cols_phase_a<TR, BW>), dim3(blocksAC), dim3(kColsThreads), 0, s, inst, ninst);
+    hipLaunchKernelGGL((cols_phase_b<BW>), dim3(blocksB), dim3(kColsThreads), 0, s, inst, ninst);
+    hipLaunchKernelGGL((cols_phase_c<TR, TX, BW, EPI>), dim3(blocksAC), dim3(kColsThreads), 0, s,
+                       inst, ninst);
+    return hipGetLastError();
+}
+
+template <typename TR, typename TX, int EPI>
+hipError_t cols_bw(int bw, const ColsInst *inst, int ninst, int blocksAC, int blocksB,
+                   hipStream_t s) {
+    return bw == 1 ? cols_one<TR, TX, 1, EPI>(inst, ninst, blocksAC, blocksB, s)
+                   : cols_one<TR, TX, 2, EPI>(inst, ninst, blocksAC, blocksB, s);
+}
+
+}  // namespace
+
+hipError_t launch_ragged_lines(int dtype, int bw, const RaggedLines &a, int grid, size_t lds,
+                               hipStream_t s) {
+    switch (dtype * 2 + (bw - 1)) {
+    case F64 * 2 + 0: return ragged_one<double, 1>(a, grid, lds, s);
+    case F64 * 2 + 1: return ragged_one<double, 2>(a, grid, lds, s);
+    case F32 * 2 + 0: return ragged_one<float, 1>(a, grid, lds, s);
+    case F32 * 2 + 1: return ragged_one<float, 2>(a, grid, lds, s);
+    case BF16 * 2 + 0: return ragged_one<bf16, 1>(a, grid, lds, s);
+    case BF16 * 2 + 1: return ragged_one<bf16, 2>(a, grid, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_rows(int dtype, int bw, const RowsInst *inst, int ninst, int nlines, int grid,
+                       size_t lds, hipStream_t s) {
+    switch (dtype * 2 + (bw - 1)) {
+    case F64 * 2 + 0: return rows_one<double, 1>(inst, ninst, nlines, grid, lds, s);
+    case F64 * 2 + 1: return rows_one<double, 2>(inst, ninst, nlines, grid, lds, s);
+    case F32 * 2 + 0: return rows_one<float, 1>(inst, ninst, nlines, grid, lds, s);
+    case F32 * 2 + 1: return rows_one<float, 2>(inst, ninst, nlines, grid, lds, s);
+    case BF16 * 2 + 0: return rows_one<bf16, 1>(inst, ninst, nlines, grid, lds, s);
+    case BF16 * 2 + 1: return rows_one<bf16, 2>(inst, ninst, nlines, grid, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_cols(int rhs_dtype, int x_dtype, int bw, int epilogue, const ColsInst *inst,
+                       int ninst, int blocksAC, int blocksB, hipStream_t s) {
+    if (bw != 1 && bw != 2) return hipErrorInvalidValue;
+    if (epilogue == 0) {
+        if (rhs_dtype == F64 && x_dtype == F64) return cols_bw<double, double, 0>(bw, inst, ninst, blocksAC, blocksB, s);
+        if (rhs_dtype == F32 && x_dtype == F32) return cols_bw<float, float, 0>(bw, inst, ninst, blocksAC, blocksB, s);
+        if (rhs_dtype == BF16 && x_dtype == BF16) return cols_bw<bf16, bf16, 0>(bw, inst, ninst, blocksAC, blocksB, s);
+    } else if (bw == 2) {
+        if (rhs_dtype == F64 && x_dtype == F64) return cols_one<double, double, 2, 1>(inst, ninst, blocksAC, blocksB, s);
+        if (rhs_dtype == F32 && x_dtype == F32) return cols_one<float, float, 2, 1>(inst, ninst, blocksAC, blocksB, s);
+        if (rhs_dtype == F32 && x_dtype == BF16) return cols_one<float, bf16, 2, 1>(inst, ninst, blocksAC, blocksB, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace mxs

@@ -1,0 +1,85 @@
+// Cyclic banded line solves: shared structures of the kernels and the plans.
+//
+// A symmetric positive-definite circulant with bands c[0..bw] (bw = 1, 2) is
+// factored exactly as A = K P(S) P(S^-1), with S the cyclic shift
+// ((S y)_i = y_{i-1}) and P(z) = 1 - p1 z - p2 z^2 holding the roots of the
+// symbol inside the unit circle (spectral factorisation of the symbol).
+// A x = r is then solved by two cyclic linear recurrences:
+//     forward   y_i = r_i + p1 y_{i-1} + p2 y_{i-2}   (indices mod n)
+//     backward  u_i = y_i + p1 u_{i+1} + p2 u_{i+2}
+// and x = u / K.  Both recurrences are stable (|roots| < 1).
+#pragma once
+
+#include "mxs_internal.h"
+
+namespace mxs {
+
+struct CyclicFactor {
+    double p1 = 0, p2 = 0, K = 1, invK = 1;
+};
+
+// Factor the symmetric circulant with bands c[0..bw].  Returns 0 on success,
+// -1 for invalid input, -2 when the symbol is not positive on the circle.
+int factor_symmetric_circulant(int bw, const double *c, CyclicFactor *f);
+
+// Chunk length (even) of a line of n elements spread over the 64 lanes of a
+// wavefront; chunk l is stored in LDS at l * (k + 1).
+inline int wave_chunk(long long n) {
+    long long k = (n + 127) / 128 * 2;
+    return static_cast<int>(k < 2 ? 2 : k);
+}
+inline size_t wave_line_lds_bytes(int k) { return static_cast<size_t>(64) * (k + 1) * sizeof(double); }
+
+// --- lines solved by one wavefront each --------------------------------------
+struct RaggedLines {
+    const void *in;
+    void *out;
+    const long long *offsets;   // device, nbatch + 1
+    const int *order;           // device, lines by decreasing length
+    int nlines;
+    double p1, p2, invK;
+};
+
+struct RowsInst {
+    const void *in;
+    void *out;
+    long long ld;
+    int nx, ny;
+    int line0;                  // first global line index of this instance
+    double p1, p2, invK;
+};
+
+// --- columns: three phases over segments of kSeg rows -------------------------
+constexpr int kSeg = 32;
+constexpr int kColsThreads = 256;
+
+struct ColsInst {
+    const void *rhs;            // rhs dtype
+    void *x;                    // output dtype
+    const void *cur;            // CH update: C^n (output dtype), or nullptr
+    const void *prev;           // CH update: C^{n-1} (output dtype), or nullptr
+    double *carry;              // [nseg][4][nx] doubles
+    long long ld;
+    int nx, ny;
+    int nstrips, nseg;
+    int blk0;                   // first block of phases A and C
+    int blkB0;                  // first block of phase B
+    double p1, p2, invK;
+    double Tf[4], Tl[4];        // M^kSeg and M^(last segment length), row-major
+    double Qf[4], Ql[4];        // top state of the backward pass over the forward homogeneous response
+    double Cinv[4];             // (I - M^n)^-1
+};
+
+// Fill the column coefficients of an instance with n = ny rows.
+void fill_cols_coef(const CyclicFactor &f, int bw, int ny, ColsInst *ci);
+
+hipError_t launch_ragged_lines(int dtype, int bw, const RaggedLines &a, int grid, size_t lds,
+                               hipStream_t s);
+hipError_t launch_rows(int dtype, int bw, const RowsInst *inst, int ninst, int nlines, int grid,
+                       size_t lds, hipStream_t s);
+// epilogue: 0 = x = A^-1 rhs; 1 = Cahn-Hilliard update x = 2 cur - prev + A^-1 rhs.
+// (rhs dtype, output dtype) pairs: (F64,F64), (F32,F32), (BF16,BF16), (F32,BF16).
+hipError_t launch_cols(int rhs_dtype, int x_dtype, int bw, int epilogue, const ColsInst *inst,
+                       int ninst, int blocksAC, int blocksB, hipStream_t s);
+
+}  // namespace mxs

@@ -1,0 +1,215 @@
+// Plan for batched cyclic banded solves (mxs_create_cyclic_solve).
+#include "plans.h"
+#include "solve.h"
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+namespace mxs {
+
+int device_lds_per_cu() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+            hipSuccess || v <= 0)
+        return 65536;
+    return v;
+}
+
+// Persistent grid for one-wavefront-per-line kernels: as many blocks as the
+// LDS of the device holds at once, at most one per line.
+int wave_grid(long long nlines, size_t lds_bytes) {
+    const long long per_cu = std::max<long long>(1, std::min<long long>(16, device_lds_per_cu() / std::max<size_t>(lds_bytes, 1)));
+    return static_cast<int>(std::max<long long>(1, std::min<long long>(nlines, per_cu * device_cu_count())));
+}
+
+namespace {
+
+struct SolvePlan final : mxs_plan_s {
+    int geometry = 0, bw = 1, dtype = F64;
+    CyclicFactor f;
+    // ragged
+    RaggedLines rl{};
+    DevBuf offsets, order;
+    // rows / cols
+    RowsInst rows{};
+    ColsInst cols{};
+    DevBuf table, carry;
+    int nlines = 0, grid = 1, blocksAC = 0, blocksB = 0;
+    size_t lds = 0, bytes = 0;
+    bool dirty = true;
+    SolvePlan() : mxs_plan_s(KIND_SOLVE) {}
+
+    mxs_status set_io(const void *rhs, void *x) {
+        if (!rhs || !x) return fail(MXS_ERR_INVALID_ARG, "rhs/x must be device pointers");
+        if (rhs != x && ranges_overlap(rhs, bytes, x, bytes))
+            return fail(MXS_ERR_ALIAS, "rhs and x overlap without being the same buffer");
+        rl.in = rhs;
+        rl.out = x;
+        rows.in = rhs;
+        rows.out = x;
+        cols.rhs = rhs;
+        cols.x = x;
+        dirty = true;
+        return MXS_OK;
+    }
+
+    mxs_status compute(hipStream_t s) override {
+        hipError_t e = hipSuccess;
+        if (geometry == MXS_LINES_RAGGED) {
+            e = launch_ragged_lines(dtype, bw, rl, grid, lds, s);
+        } else if (geometry == MXS_LINES_ROWS) {
+            if (dirty) {
+                e = hipMemcpyAsync(table.ptr, &rows, sizeof rows, hipMemcpyHostToDevice, s);
+                dirty = false;
+            }
+            if (e == hipSuccess)
+                e = launch_rows(dtype, bw, static_cast<const RowsInst *>(table.ptr), 1, nlines, grid,
+                                lds, s);
+        } else {
+            if (dirty) {
+                e = hipMemcpyAsync(table.ptr, &cols, sizeof cols, hipMemcpyHostToDevice, s);
+                dirty = false;
+            }
+            if (e == hipSuccess)
+                e = launch_cols(dtype, dtype, bw, 0, static_cast<const ColsInst *>(table.ptr), 1,
+                                blocksAC, blocksB, s);
+        }
+        return e == hipSuccess ? MXS_OK : hip_fail(e, "cyclic solve launch");
+    }
+    mxs_status swap() override {
+        const void *r = rl.in;
+        return set_io(rl.out, const_cast<void *>(r));
+    }
+    mxs_status rebind(const void *in, void *out) override { return set_io(in, out); }
+};
+
+}  // namespace
+}  // namespace mxs
+
+using namespace mxs;
+
+extern "C" mxs_status mxs_create_cyclic_solve(int bw, const double *coef, int geometry, int nx,
+                                              int ny, long long ld, int nbatch,
+                                              const long long *offsets, int dtype,
+                                              const void *rhs, void *x, mxs_plan *plan) {
+    if (!plan) return fail(MXS_ERR_INVALID_ARG, "plan output pointer is NULL");
+    *plan = nullptr;
+    if (bw != 1 && bw != 2) return fail(MXS_ERR_INVALID_ARG, "bw must be 1 or 2");
+    if (!coef) return fail(MXS_ERR_INVALID_ARG, "coef is NULL");
+    if (!valid_dtype(dtype)) return fail(MXS_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+    if (geometry != MXS_LINES_RAGGED && geometry != MXS_LINES_ROWS && geometry != MXS_LINES_COLS)
+        return fail(MXS_ERR_INVALID_ARG, "unknown geometry %d", geometry);
+    const int minlen = 2 * bw + 1;
+    constexpr long long kMaxLine = 16384;
+
+    SolvePlan *p = new (std::nothrow) SolvePlan();
+    if (!p) return fail(MXS_ERR_OOM, "host allocation failed");
+    p->geometry = geometry;
+    p->bw = bw;
+    p->dtype = dtype;
+    const int fst = factor_symmetric_circulant(bw, coef, &p->f);
+    if (fst) {
+        delete p;
+        return fst == -2 ? fail(MXS_ERR_UNSUPPORTED, "the circulant is not symmetric positive definite")
+                         : fail(MXS_ERR_INVALID_ARG, "invalid band coefficients");
+    }
+    mxs_status st;
+    hipError_t e = hipSuccess;
+    if (geometry == MXS_LINES_RAGGED) {
+        if (nbatch <= 0 || !offsets) {
+            delete p;
+            return fail(MXS_ERR_INVALID_ARG, "ragged lines need nbatch > 0 and host offsets");
+        }
+        if (offsets[0] != 0) {
+            delete p;
+            return fail(MXS_ERR_INVALID_ARG, "offsets[0] must be 0");
+        }
+        long long nmax = 0;
+        std::vector<long long> len(nbatch);
+        for (int b = 0; b < nbatch; ++b) {
+            len[b] = offsets[b + 1] - offsets[b];
+            if (len[b] < minlen || len[b] > kMaxLine) {
+                delete p;
+                return fail(len[b] < minlen ? MXS_ERR_INVALID_ARG : MXS_ERR_UNSUPPORTED,
+                            "line %d has length %lld outside [%d, %lld]", b, len[b], minlen, kMaxLine);
+            }
+            nmax = std::max(nmax, len[b]);
+        }
+        p->bytes = static_cast<size_t>(offsets[nbatch]) * dtype_size(dtype);
+        if ((st = p->set_io(rhs, x))) {
+            delete p;
+            return st;
+        }
+        std::vector<int> order(nbatch);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return len[a] > len[b]; });
+        if ((e = p->offsets.upload(offsets, sizeof(long long) * (nbatch + 1))) != hipSuccess ||
+            (e = p->order.upload(order.data(), sizeof(int) * nbatch)) != hipSuccess) {
+            delete p;
+            return hip_fail(e, "line tables upload");
+        }
+        p->rl.offsets = static_cast<const long long *>(p->offsets.ptr);
+        p->rl.order = static_cast<const int *>(p->order.ptr);
+        p->rl.nlines = nbatch;
+        p->rl.p1 = p->f.p1;
+        p->rl.p2 = bw == 2 ? p->f.p2 : 0.0;
+        p->rl.invK = p->f.invK;
+        p->lds = wave_line_lds_bytes(wave_chunk(nmax));
+        p->grid = wave_grid(nbatch, p->lds);
+    } else {
+        if (nx <= 0 || ny <= 0 || ld < nx) {
+            delete p;
+            return fail(MXS_ERR_INVALID_ARG, "need nx, ny > 0 and ld >= nx");
+        }
+        const long long n = geometry == MXS_LINES_ROWS ? nx : ny;
+        if (n < minlen || (geometry == MXS_LINES_ROWS && n > kMaxLine)) {
+            delete p;
+            return fail(n < minlen ? MXS_ERR_INVALID_ARG : MXS_ERR_UNSUPPORTED,
+                        "line length %lld outside [%d, %lld]", n, minlen, kMaxLine);
+        }
+        p->bytes = grid_bytes(nx, ny, ld, dtype);
+        if ((st = p->set_io(rhs, x))) {
+            delete p;
+            return st;
+        }
+        if (geometry == MXS_LINES_ROWS) {
+            p->rows.ld = ld;
+            p->rows.nx = nx;
+            p->rows.ny = ny;
+            p->rows.line0 = 0;
+            p->rows.p1 = p->f.p1;
+            p->rows.p2 = bw == 2 ? p->f.p2 : 0.0;
+            p->rows.invK = p->f.invK;
+            p->nlines = ny;
+            p->lds = wave_line_lds_bytes(wave_chunk(nx));
+            p->grid = wave_grid(ny, p->lds);
+            e = p->table.alloc(sizeof(RowsInst));
+        } else {
+            fill_cols_coef(p->f, bw, ny, &p->cols);
+            p->cols.ld = ld;
+            p->cols.nx = nx;
+            p->cols.ny = ny;
+            p->cols.nstrips = (nx + kColsThreads - 1) / kColsThreads;
+            p->cols.blk0 = 0;
+            p->cols.blkB0 = 0;
+            p->blocksAC = p->cols.nstrips * p->cols.nseg;
+            p->blocksB = p->cols.nstrips;
+            e = p->carry.alloc(sizeof(double) * 4 * static_cast<size_t>(nx) * p->cols.nseg);
+            if (e == hipSuccess) e = p->table.alloc(sizeof(ColsInst));
+            p->cols.carry = static_cast<double *>(p->carry.ptr);
+        }
+        if (e != hipSuccess) {
+            delete p;
+            return hip_fail(e, "solve scratch allocation");
+        }
+    }
+    if (p->lds > static_cast<size_t>(device_lds_limit())) {
+        delete p;
+        return fail(MXS_ERR_UNSUPPORTED, "line too long for the LDS of one workgroup");
+    }
+    register_plan(p);
+    *plan = p;
+    return MXS_OK;
+}

@@ -1,0 +1,231 @@
+"""GPU parity of the ADI Cahn-Hilliard step (single grid and ensemble).
+
+FP64: C^n and C^{n-1} within 1e-12 relative (normwise) of the oracle; the
+mass drift |M^n - M^0| / sum|C^0| at most 1e-12 over the run.  FP32 and BF16
+storage: the error against the FP64 oracle, run from the same rounded
+initial data, is measured and held under the bounds stated in the tests.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1902_09931_amd import workloads as wl
+from tests.gpu_util import TORCH, code, rel_err, round_to, torch
+
+pytestmark = pytest.mark.gpu
+
+b = pytest.importorskip("paper_1902_09931_amd.binding")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+D, GAMMA = 1.0, 0.01
+
+
+def ptr_tensor(addr, like):
+    """The torch tensor among `like` whose storage starts at addr."""
+    for t in like:
+        if t.data_ptr() == addr:
+            return t
+    raise AssertionError("state pointer not among the buffers")
+
+
+class Grid:
+    def __init__(self, c0, dt_name="f64", c_prev=None, dt=None, dx=None, dy=None):
+        ny, nx = c0.shape
+        self.dx = dx or 2 * math.pi / nx
+        self.dy = dy or 2 * math.pi / ny
+        self.dt = dt or 0.1 * self.dx * self.dx
+        tdt = TORCH[dt_name]
+        self.bufs = [torch.from_numpy(np.ascontiguousarray(c0 if c_prev is None else c_prev)).to(tdt).cuda(),
+                     torch.from_numpy(np.ascontiguousarray(c0)).to(tdt).cuda(),
+                     torch.zeros((ny, nx), dtype=tdt, device="cuda")]
+        self.plan = b.mxs_ch_create(nx, ny, self.dx, self.dy, self.dt, D, GAMMA, code(dt_name), *self.bufs)
+
+    def state(self):
+        p, c = b.mxs_ch_state(self.plan)
+        return (ptr_tensor(p, self.bufs).double().cpu().numpy(),
+                ptr_tensor(c, self.bufs).double().cpu().numpy())
+
+    def close(self):
+        b.mxs_destroy(self.plan)
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (48, 80), (33, 40)])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_ch_small_grids_f64(shape, use_graph):
+    ny, nx = shape
+    c0 = wl.ch_initial(ny, nx, seed=2)
+    g = Grid(c0)
+    try:
+        b.mxs_ch_step(g.plan, 50, use_graph)
+        torch.cuda.synchronize()
+        assert b.mxs_ch_steps_taken(g.plan) == 50
+        gp, gc = g.state()
+        op, oc = oracle.ch_run(c0, c0, 50, g.dx, g.dy, g.dt, D, GAMMA)
+        assert rel_err(gc, oc) <= 1e-12
+        assert rel_err(gp, op) <= 1e-12
+    finally:
+        g.close()
+
+
+def test_ch_first_step_spectral_closed_form():
+    """The GPU step against the closed form of one step from
+    C^{-1} = C^0 = A cos(kx) cos(ly) (independent of the oracle)."""
+    ny, nx = 32, 48
+    dx, dy = 2 * math.pi / nx, 2 * math.pi / ny
+    y, x = np.meshgrid(np.arange(ny) * dy, np.arange(nx) * dx, indexing="ij")
+    A, k, l = 0.6, 2, 3
+    c0 = A * np.cos(k * x) * np.cos(l * y)
+    dt = 0.1 * dx
+    g = Grid(c0, dt=dt)
+    try:
+        b.mxs_ch_step(g.plan, 1, False)
+        torch.cuda.synchronize()
+        _, got = g.state()
+    finally:
+        g.close()
+    S = lambda kappa, h: 4 * math.sin(kappa * h / 2) ** 2 / h ** 2
+    a = 2.0 / 3.0 * D * GAMMA * dt
+    F = {(1, 1): 9 * A ** 3 / 16 - A, (1, 3): 3 * A ** 3 / 16, (3, 1): 3 * A ** 3 / 16, (3, 3): A ** 3 / 16}
+    expect = c0.copy()
+    for (p, q), f in F.items():
+        sx, sy = S(p * k, dx), S(q * l, dy)
+        r = 2.0 / 3.0 * D * dt * (-(sx + sy)) * f - (a * (sx + sy) ** 2 * A if (p, q) == (1, 1) else 0.0)
+        expect += r / ((1 + a * sx ** 2) * (1 + a * sy ** 2)) * np.cos(p * k * x) * np.cos(q * l * y)
+    assert np.abs(got - expect).max() <= 1e-13
+
+
+def test_ch_graph_replays_match_eager():
+    """Graph replays (one graph per buffer rotation) give bit-identical states
+    to eager launches, step after step, with eager work and synchronisation
+    between replays."""
+    c0 = wl.ch_initial(96, 96, seed=4)
+    ge, gg = Grid(c0), Grid(c0)
+    try:
+        for k in range(7):
+            b.mxs_ch_step(ge.plan, 1, False)
+            b.mxs_ch_step(gg.plan, 1, True)
+            torch.cuda.synchronize()
+            _ = torch.ones(1000, device="cuda").sum().item()
+            assert np.array_equal(ge.state()[1], gg.state()[1]), k
+    finally:
+        ge.close()
+        gg.close()
+
+
+def test_ch_1024_mass_and_parity():
+    """1024^2 FP64, dt = 0.1 dx^2: parity with the oracle after 3 steps, then
+    mass conserved to 1e-12 over 1000 steps."""
+    n = 1024
+    c0 = wl.ch_initial(n, n, seed=2)
+    g = Grid(c0)
+    try:
+        m0 = b.mxs_ch_mass(g.plan)[0]
+        assert abs(m0 - oracle.mass(c0)) <= 1e-12 * np.abs(c0).sum()
+        b.mxs_ch_step(g.plan, 3, True)
+        torch.cuda.synchronize()
+        op, oc = oracle.ch_run(c0, c0, 3, g.dx, g.dy, g.dt, D, GAMMA)
+        gp, gc = g.state()
+        assert rel_err(gc, oc) <= 1e-12
+        b.mxs_ch_step(g.plan, 997, True)
+        m = b.mxs_ch_mass(g.plan)[0]
+        assert abs(m - m0) / np.abs(c0).sum() <= 1e-12
+        _, gc = g.state()
+        assert abs(oracle.mass(gc) - m) <= 1e-12 * np.abs(c0).sum()
+    finally:
+        g.close()
+
+
+def test_ch_4096_one_step_parity():
+    n = 4096
+    c0 = wl.ch_initial(n, n, seed=2)
+    g = Grid(c0)
+    try:
+        b.mxs_ch_step(g.plan, 2, True)
+        torch.cuda.synchronize()
+        gp, gc = g.state()
+    finally:
+        g.close()
+    op, oc = oracle.ch_run(c0, c0, 2, g.dx, g.dy, g.dt, D, GAMMA)
+    assert rel_err(gc, oc) <= 1e-12
+
+
+@pytest.mark.parametrize("dt_name,bound", [("f32", 1e-4), ("bf16", 1e-1)])
+def test_ch_reduced_precision_error(dt_name, bound):
+    """FP32 / BF16 storage against the FP64 oracle from the same rounded
+    initial data, 200 steps on 128^2: relative error under the stated bound,
+    and the mass (summed in double) still conserved to the storage
+    precision."""
+    n = 128
+    c0 = round_to(wl.ch_initial(n, n, seed=7), dt_name)
+    g = Grid(c0, dt_name)
+    try:
+        m0 = b.mxs_ch_mass(g.plan)[0]
+        b.mxs_ch_step(g.plan, 200, True)
+        torch.cuda.synchronize()
+        _, gc = g.state()
+        m = b.mxs_ch_mass(g.plan)[0]
+    finally:
+        g.close()
+    _, oc = oracle.ch_run(c0, c0, 200, g.dx, g.dy, g.dt, D, GAMMA)
+    err = rel_err(gc, oc)
+    print(f"{dt_name}: relative error after 200 steps {err:.3e}, mass drift "
+          f"{abs(m - m0) / np.abs(c0).sum():.3e}")
+    assert err <= bound
+
+
+def test_ch_ensemble_matches_single_grids_and_oracle():
+    """An ensemble of grids of mixed sizes advances as the separate grids do
+    (bit-identical), and matches the oracle per instance."""
+    sizes = [(64, 64), (96, 96), (40, 72), (128, 128), (64, 64)]
+    c0s = [wl.ch_initial(ny, nx, seed=10 + k) for k, (ny, nx) in enumerate(sizes)]
+    nsteps = 20
+    bufs = []
+    for c0 in c0s:
+        ny, nx = c0.shape
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        bufs.append([t(c0), t(c0), torch.zeros((ny, nx), dtype=torch.float64, device="cuda")])
+    nx = [s[1] for s in sizes]
+    ny = [s[0] for s in sizes]
+    dxs = [2 * math.pi / v for v in nx]
+    dys = [2 * math.pi / v for v in ny]
+    dts = [0.1 * d * d for d in dxs]
+    plan = b.mxs_ch_ensemble_create(nx, ny, dxs, dys, dts, D, GAMMA, b.MXS_F64,
+                                    [q[0] for q in bufs], [q[1] for q in bufs], [q[2] for q in bufs])
+    try:
+        b.mxs_ch_step(plan, nsteps, True)
+        torch.cuda.synchronize()
+        masses = b.mxs_ch_mass(plan, len(sizes))
+        for k, c0 in enumerate(c0s):
+            _, cur = b.mxs_ch_state(plan, k)
+            got = ptr_tensor(cur, bufs[k]).cpu().numpy()
+            g = Grid(c0)
+            b.mxs_ch_step(g.plan, nsteps, False)
+            torch.cuda.synchronize()
+            assert np.array_equal(got, g.state()[1])
+            g.close()
+            _, oc = oracle.ch_run(c0, c0, nsteps, dxs[k], dys[k], dts[k], D, GAMMA)
+            assert rel_err(got, oc) <= 1e-12
+            assert abs(masses[k] - oracle.mass(c0)) <= 1e-12 * np.abs(c0).sum()
+    finally:
+        b.mxs_destroy(plan)
+
+
+def test_ch_argument_errors():
+    a = torch.zeros((16, 16), dtype=torch.float64, device="cuda")
+    c = torch.zeros_like(a)
+    d = torch.zeros_like(a)
+    with pytest.raises(b.MxsError) as e:
+        b.mxs_ch_create(16, 16, 0.1, 0.1, 0.01, 1.0, 0.01, b.MXS_F64, a, a, d)
+    assert e.value.status == b.MXS_ERR_ALIAS
+    with pytest.raises(b.MxsError) as e:
+        b.mxs_ch_create(4, 16, 0.1, 0.1, 0.01, 1.0, 0.01, b.MXS_F64, a, c, d)
+    assert e.value.status == b.MXS_ERR_INVALID_ARG
+    with pytest.raises(b.MxsError) as e:
+        b.mxs_ch_create(16, 16, 0.1, 0.1, -1.0, 1.0, 0.01, b.MXS_F64, a, c, d)
+    assert e.value.status == b.MXS_ERR_INVALID_ARG
+    with pytest.raises(b.MxsError) as e:
+        b.mxs_ch_step(0x5678, 1, False)
+    assert e.value.status == b.MXS_ERR_BAD_HANDLE

@@ -1,0 +1,137 @@
+"""GPU parity of the batched cyclic banded solves against the oracle.
+
+FP64: 1e-12 relative (normwise) against the oracle's banded LU + Woodbury
+solve.  FP32/BF16 storage (elimination in double): the only extra error is
+the rounding of the result to the storage dtype, so |err| <= u_s |x| +
+1e-12 max|x|.  Both sides read the same rounded right-hand side.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1902_09931_amd import workloads as wl
+from tests.gpu_util import U_STORE, code, rel_err, round_to, to_device, to_host, torch
+
+pytestmark = pytest.mark.gpu
+
+b = pytest.importorskip("paper_1902_09931_amd.binding")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+TRI = [2.5, -1.0]                                   # circ(-1, 2 + sigma, -1), sigma = 0.5
+PENTA = [1 + 6 * 283.0, -4 * 283.0, 283.0]          # I + beta [1, -4, 6, -4, 1]
+PENTA_SMALL = [1 + 6 * 17.7, -4 * 17.7, 17.7]
+OTHER = [5.0, 1.0, 0.8]                             # a symmetric positive definite pentadiagonal
+
+
+def check(got, ref, dt):
+    if dt == "f64":
+        assert rel_err(got, ref) <= 1e-12
+    else:
+        bound = U_STORE[dt] * np.abs(ref) + 1e-12 * np.abs(ref).max()
+        assert np.all(np.abs(got - ref) <= bound)
+
+
+@pytest.mark.parametrize("coef", [TRI, PENTA, OTHER])
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+def test_ragged_lines(coef, dt):
+    bw = len(coef) - 1
+    rng = np.random.default_rng(7 + bw)
+    lengths = rng.permutation([5, 6, 7, 63, 64, 65, 127, 128, 129, 1000, 4096, 300, 2 * bw + 1])
+    offs = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    r = rng.uniform(-1, 1, offs[-1])
+    rr = round_to(r, dt)
+    drhs = to_device(r, dt)
+    dx = torch.empty_like(drhs)
+    p = b.mxs_create_cyclic_solve(bw, coef, b.MXS_LINES_RAGGED, 0, 0, 0, offs, code(dt), drhs, dx)
+    b.mxs_compute(p)
+    torch.cuda.synchronize()
+    b.mxs_destroy(p)
+    ref = oracle.cyclic_solve_batch(oracle.circulant_bands(coef), offs, rr)
+    check(dx.double().cpu().numpy(), ref, dt)
+
+
+@pytest.mark.parametrize("shape", [(37, 45), (70, 1030), (257, 129), (5, 7), (33, 64)])
+@pytest.mark.parametrize("coef", [TRI, PENTA, PENTA_SMALL])
+@pytest.mark.parametrize("geometry", ["rows", "cols"])
+def test_grid_lines_f64(shape, coef, geometry):
+    bw = len(coef) - 1
+    ny, nx = shape
+    if (nx if geometry == "rows" else ny) < 2 * bw + 1:
+        pytest.skip("line shorter than the band")
+    rng = np.random.default_rng(ny * 1000 + nx)
+    r = rng.uniform(-1, 1, shape)
+    drhs = to_device(r, "f64")
+    dx = torch.empty_like(drhs)
+    geo = b.MXS_LINES_ROWS if geometry == "rows" else b.MXS_LINES_COLS
+    p = b.mxs_create_cyclic_solve(bw, coef, geo, nx, ny, nx, None, b.MXS_F64, drhs, dx)
+    b.mxs_compute(p)
+    torch.cuda.synchronize()
+    b.mxs_destroy(p)
+    ref = oracle.cyclic_solve_grid(oracle.circulant_bands(coef), 1 if geometry == "rows" else 0, r)
+    check(to_host(dx), ref, "f64")
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+@pytest.mark.parametrize("geometry", ["rows", "cols"])
+def test_grid_lines_reduced_storage_in_place_and_pitch(dt, geometry):
+    """Reduced-precision storage, a row pitch larger than nx, and the in-place
+    form (rhs == x)."""
+    ny, nx, ld = 100, 77, 80
+    rng = np.random.default_rng(5)
+    r = rng.uniform(-1, 1, (ny, nx))
+    rr = round_to(r, dt)
+    buf = to_device(r, dt, ld)
+    geo = b.MXS_LINES_ROWS if geometry == "rows" else b.MXS_LINES_COLS
+    p = b.mxs_create_cyclic_solve(2, PENTA, geo, nx, ny, ld, None, code(dt), buf, buf)
+    b.mxs_compute(p)
+    torch.cuda.synchronize()
+    b.mxs_destroy(p)
+    ref = oracle.cyclic_solve_grid(oracle.circulant_bands(PENTA), 1 if geometry == "rows" else 0, rr)
+    check(to_host(buf, nx), ref, dt)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_full_batch_tridiagonal(dt):
+    """65536 periodic lines, lengths U{64..4096}, circ(-1, 2.5, -1): every
+    output against the oracle."""
+    lengths, offs = wl.ragged_lengths()
+    r = np.random.default_rng(5).uniform(-1, 1, int(offs[-1]))
+    rr = round_to(r, dt)
+    drhs = to_device(r, dt)
+    dx = torch.empty_like(drhs)
+    p = b.mxs_create_cyclic_solve(1, TRI, b.MXS_LINES_RAGGED, 0, 0, 0, offs, code(dt), drhs, dx)
+    b.mxs_compute(p)
+    torch.cuda.synchronize()
+    b.mxs_destroy(p)
+    ref = oracle.cyclic_solve_batch(oracle.circulant_bands(TRI), offs, rr)
+    check(dx.double().cpu().numpy(), ref, dt)
+
+
+def test_swap_solves_twice():
+    r = np.random.default_rng(9).uniform(-1, 1, (40, 50))
+    a = to_device(r, "f64")
+    c = torch.empty_like(a)
+    p = b.mxs_create_cyclic_solve(2, PENTA_SMALL, b.MXS_LINES_COLS, 50, 40, 50, None, b.MXS_F64, a, c)
+    b.mxs_compute(p)
+    b.mxs_swap(p)
+    b.mxs_compute(p)
+    torch.cuda.synchronize()
+    b.mxs_destroy(p)
+    bands = oracle.circulant_bands(PENTA_SMALL)
+    ref = oracle.cyclic_solve_grid(bands, 0, oracle.cyclic_solve_grid(bands, 0, r))
+    check(to_host(a), ref, "f64")
+
+
+def test_solve_argument_errors():
+    a = torch.zeros(64, dtype=torch.float64, device="cuda")
+    c = torch.zeros_like(a)
+    with pytest.raises(b.MxsError) as e:      # not positive definite
+        b.mxs_create_cyclic_solve(1, [1.0, 0.6], b.MXS_LINES_RAGGED, 0, 0, 0, [0, 64], b.MXS_F64, a, c)
+    assert e.value.status == b.MXS_ERR_UNSUPPORTED
+    with pytest.raises(b.MxsError) as e:      # line shorter than 2 bw + 1
+        b.mxs_create_cyclic_solve(2, PENTA, b.MXS_LINES_RAGGED, 0, 0, 0, [0, 4, 64], b.MXS_F64, a, c)
+    assert e.value.status == b.MXS_ERR_INVALID_ARG
+    with pytest.raises(b.MxsError) as e:      # partial overlap
+        b.mxs_create_cyclic_solve(1, TRI, b.MXS_LINES_RAGGED, 0, 0, 0, [0, 32], b.MXS_F64, a, a[1:])
+    assert e.value.status == b.MXS_ERR_ALIAS
