@@ -13,8 +13,11 @@ updated per second (8 x 8192^2 per step).
 The JSON line also carries the roofline of the dominant kernel (its average
 launch time taken with HIP events on the stream it runs on, against the
 algorithmic 16 bytes per point), the oracle timed on the host cores on a
-bounded sample, and further sections (FP32 stencil set, batched ragged 1D
-stencils) under "extra".  Only the cpu_baseline leg uses the oracle.
+bounded sample, and further sections under "extra": the FP32 stencil set,
+batched ragged 1D stencils and cyclic tridiagonal solves (65536 lines), the
+ADI Cahn-Hilliard step on 1024^2 and 4096^2 FP64 grids (steps/s), the
+64-grid FP32/BF16 ensemble against the FP64 path, and a device copy ceiling.
+Only the cpu_baseline leg uses the oracle.
 """
 import argparse
 import json
@@ -104,6 +107,99 @@ def bench_ragged_1d(torch, b, wl, dt, steps, warmup):
             "frac_hbm_peak": nbytes / per / 1e9 / HBM_PEAK_GBS}
 
 
+def bench_cyclic_tri(torch, b, wl, dt, steps, warmup):
+    """65536 periodic lines, lengths U{64..4096}: A x = r with circ(-1, 2.5, -1)."""
+    tdt = {"f64": torch.float64, "f32": torch.float32}[dt]
+    code = {"f64": b.MXS_F64, "f32": b.MXS_F32}[dt]
+    lengths, offs = wl.ragged_lengths()
+    total = int(offs[-1])
+    import numpy as np
+    r = torch.from_numpy(np.random.default_rng(5).uniform(-1, 1, total)).to(tdt).cuda()
+    x = torch.empty_like(r)
+    p = b.mxs_create_cyclic_solve(1, [2.5, -1.0], b.MXS_LINES_RAGGED, 0, 0, 0, offs, code, r, x)
+    sec, _ = time_loop(torch, lambda: b.mxs_compute(p), steps, warmup)
+    b.mxs_destroy(p)
+    per = sec / steps
+    nbytes = 2 * total * r.element_size()
+    return {"points": total, "lines": int(len(lengths)), "s_per_pass": per,
+            "gpoints_per_s": total / per / 1e9, "gb_per_s": nbytes / per / 1e9,
+            "frac_hbm_peak": nbytes / per / 1e9 / HBM_PEAK_GBS}
+
+
+def ch_buffers(torch, c0, tdt):
+    a = torch.from_numpy(c0).to(tdt).cuda()
+    return [a, a.clone(), torch.zeros_like(a)]
+
+
+def bench_ch(torch, b, wl, n, steps, warmup):
+    """Periodic n x n FP64 ADI Cahn-Hilliard, dt = 0.1 dx^2, D = 1, gamma = 0.01."""
+    import math
+    c0 = wl.ch_initial(n, n, seed=2)
+    dx = 2 * math.pi / n
+    bufs = ch_buffers(torch, c0, torch.float64)
+    p = b.mxs_ch_create(n, n, dx, dx, 0.1 * dx * dx, 1.0, 0.01, b.MXS_F64, *bufs)
+    sec, _ = time_loop(torch, lambda: b.mxs_ch_step(p, 1, True), steps, warmup)
+    m = b.mxs_ch_mass(p)[0]
+    b.mxs_destroy(p)
+    per = sec / steps
+    floor = 56 * n * n
+    return {"steps_timed": steps, "s_per_step": per, "steps_per_s": 1.0 / per,
+            "floor_bytes_per_step": floor, "gb_per_s_at_floor": floor / per / 1e9,
+            "frac_hbm_peak_at_floor": floor / per / 1e9 / HBM_PEAK_GBS,
+            "mass_drift": abs(m - float(c0.sum())) / float(abs(c0).sum())}
+
+
+def bench_ensemble(torch, b, wl, steps, warmup):
+    """64 grids of sizes 256^2..1024^2: FP32 and BF16 storage ensembles (one
+    launch per kernel per step, graph-replayed) against the plain FP64 path,
+    both as an FP64 ensemble and one grid at a time."""
+    import math
+    sizes = wl.ensemble_sizes()
+    c0s = wl.ensemble_initial(sizes)
+    pts = sum(n * n for n in sizes)
+    dxs = [2 * math.pi / n for n in sizes]
+    dts = [0.1 * d * d for d in dxs]
+    out = {"instances": len(sizes), "points": pts, "steps_timed": steps}
+    for name, tdt, code in (("f32", torch.float32, b.MXS_F32), ("bf16", torch.bfloat16, b.MXS_BF16),
+                            ("f64", torch.float64, b.MXS_F64)):
+        bufs = [ch_buffers(torch, c0, tdt) for c0 in c0s]
+        p = b.mxs_ch_ensemble_create(sizes, sizes, dxs, dxs, dts, 1.0, 0.01, code,
+                                     [q[0] for q in bufs], [q[1] for q in bufs], [q[2] for q in bufs])
+        sec, _ = time_loop(torch, lambda: b.mxs_ch_step(p, 1, True), steps, warmup)
+        b.mxs_destroy(p)
+        out[f"ensemble_{name}_steps_per_s"] = steps / sec
+        del bufs
+    bufs = [ch_buffers(torch, c0, torch.float64) for c0 in c0s]
+    plans = [b.mxs_ch_create(n, n, d, d, t, 1.0, 0.01, b.MXS_F64, *q)
+             for n, d, t, q in zip(sizes, dxs, dts, bufs)]
+
+    def seq_step():
+        for p in plans:
+            b.mxs_ch_step(p, 1, True)
+
+    sec, _ = time_loop(torch, seq_step, max(steps // 5, 10), 2)
+    out["f64_one_grid_at_a_time_steps_per_s"] = max(steps // 5, 10) / sec
+    for p in plans:
+        b.mxs_destroy(p)
+    del bufs
+    torch.cuda.empty_cache()
+    for name in ("f32", "bf16", "f64"):
+        out[f"ensemble_{name}_vs_f64_one_at_a_time"] = (out[f"ensemble_{name}_steps_per_s"] /
+                                                        out["f64_one_grid_at_a_time_steps_per_s"])
+    return out
+
+
+def copy_ceiling(torch):
+    """Device-to-device copy of 1 GiB (torch's copy kernel): read + write bytes / time."""
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    sec, _ = time_loop(torch, lambda: c.copy_(a), 20, 3)
+    gbs = 2 * a.numel() * 8 / (sec / 20) / 1e9
+    del a, c
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def cpu_baseline(wl, n, rows):
     """The oracle (single thread) on the same eight stencils over a
     rows x n slice of the grid."""
@@ -130,7 +226,12 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--sections", default="f32,ragged,tri,ch,ensemble,copy",
+                    help="extra sections to run (comma list)")
+    ap.add_argument("--ch-steps", type=int, default=0,
+                    help="override the Cahn-Hilliard step counts (0: 1000 at 1024^2, 200 at 4096^2)")
     args = ap.parse_args()
+    sections = set(args.sections.split(",")) if not args.no_extra else set()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -173,16 +274,31 @@ def main():
              "f64_kernels_us": {k: v * 1e6 for k, v in per_kernel.items()},
              "f64_hbm_frac_per_kernel": {k: bytes_per_launch / v / 1e9 / HBM_PEAK_GBS
                                          for k, v in per_kernel.items()}}
-    if not args.no_extra:
+    if "f32" in sections:
         log("stencil set f32")
         s32, _, pk32, _ = bench_stencil_set(torch, b, wl, n, "f32", args.steps, args.warmup)
         extra["f32_gpoints_per_s"] = pts / s32 / 1e9
         extra["f32_kernels_us"] = {k: v * 1e6 for k, v in pk32.items()}
         extra["f32_hbm_frac_per_kernel"] = {k: 2 * 4 * n * n / v / 1e9 / HBM_PEAK_GBS
                                             for k, v in pk32.items()}
-        for dt in ("f64", "f32"):
-            log(f"ragged 1D {dt}")
-            extra[f"ragged1d_{dt}"] = bench_ragged_1d(torch, b, wl, dt, args.steps, args.warmup)
+    for dt in ("f64", "f32"):
+        if "ragged" in sections:
+            log(f"ragged 1D stencil {dt}")
+            extra[f"ragged1d_stencil_{dt}"] = bench_ragged_1d(torch, b, wl, dt, args.steps, args.warmup)
+        if "tri" in sections:
+            log(f"batched cyclic tridiagonal {dt}")
+            extra[f"cyclic_tri_batch_{dt}"] = bench_cyclic_tri(torch, b, wl, dt, args.steps, args.warmup)
+    if "ch" in sections:
+        for nn in (1024, 4096):
+            log(f"Cahn-Hilliard ADI {nn}^2 f64")
+            k = args.ch_steps or (1000 if nn == 1024 else 200)
+            extra[f"ch_adi_{nn}_f64"] = bench_ch(torch, b, wl, nn, k, min(10, k))
+    if "ensemble" in sections:
+        log("Cahn-Hilliard ensemble")
+        k = args.ch_steps or 500
+        extra["ch_ensemble_64"] = bench_ensemble(torch, b, wl, k, min(10, k))
+    if "copy" in sections:
+        extra["copy_ceiling_gb_per_s"] = copy_ceiling(torch)
     result["extra"] = extra
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
