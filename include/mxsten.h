@@ -201,6 +201,20 @@ mxs_status mxs_ch_steps_taken(mxs_plan plan, long long *nsteps);
  * sum is NaN or Inf. */
 mxs_status mxs_ch_mass(mxs_plan plan, double *host_out, void *hip_stream);
 
+/* Choose the plan's launch layout by measurement: candidate layouts (rows
+ * per workgroup, tile order, threads per workgroup, streaming stores for
+ * stencils; workgroup shape for the ragged stencil) are each run a few
+ * times on the plan's own buffers and the fastest is kept.  The output
+ * buffer of the plan is written while tuning (with correct results).  Waits
+ * for the stream.  Layouts found are remembered for the rest of the process
+ * for plans of the same shape and kind.  Plans without tunable layouts
+ * return MXS_OK unchanged. */
+mxs_status mxs_autotune(mxs_plan plan, void *hip_stream);
+
+/* A one-line description of the plan's current launch layout, written to
+ * buf (at most len bytes, NUL-terminated). */
+mxs_status mxs_plan_info(mxs_plan plan, char *buf, int len);
+
 /* Free everything the plan owns (cuStenDestroy*).  NULL is accepted.  The
  * caller's buffers and streams are not touched. */
 mxs_status mxs_destroy(mxs_plan plan);

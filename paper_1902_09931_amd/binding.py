@@ -75,6 +75,8 @@ _SIGS = {
     "mxs_ch_steps_taken": [_vp, _llp],
     "mxs_ch_mass": [_vp, _dp, _vp],
     "mxs_destroy": [_vp],
+    "mxs_autotune": [_vp, _vp],
+    "mxs_plan_info": [_vp, ctypes.c_char_p, _int],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -194,6 +196,16 @@ def mxs_set_io(plan, in_, out):
 
 def mxs_destroy(plan):
     _check(_lib.mxs_destroy(plan))
+
+
+def mxs_autotune(plan, stream=None):
+    _check(_lib.mxs_autotune(plan, _stream(stream)))
+
+
+def mxs_plan_info(plan):
+    buf = ctypes.create_string_buffer(256)
+    _check(_lib.mxs_plan_info(plan, buf, 256))
+    return buf.value.decode()
 
 
 # --- Cahn-Hilliard ------------------------------------------------------------

@@ -8,11 +8,15 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <unordered_set>
 #include <vector>
+
+void mxs_plan_s::info(char *buf, int len) const { snprintf(buf, len, "plan kind %d", kind); }
 
 namespace mxs {
 
@@ -146,18 +150,46 @@ struct Stencil2DPlan final : mxs_plan_s {
     DevBuf wts;
     Stencil2DPlan() : mxs_plan_s(KIND_STENCIL2D) {}
 
-    void layout() {
+    void set_layout(int rows, int order, int nthreads, int nt) {
+        threads = nthreads;
+        a.rows = rows;
+        a.order = order;
+        a.nt_store = nt;
         const int W = threads * vec_elems(dtype);
         a.nstrips = (a.nx + W - 1) / W;
-        int rows = nwy > 1 ? 64 : 16;
-        rows = std::max(rows, 2 * nwy);
-        // keep several workgroups per CU in flight
-        const long long want = 8LL * device_cu_count();
-        while (rows > std::max(8, 2 * nwy) &&
-               static_cast<long long>(a.nstrips) * ((a.ny + rows - 1) / rows) < want)
-            rows /= 2;
-        a.rows = rows;
         a.nchunks = (a.ny + rows - 1) / rows;
+    }
+
+    // Layout before tuning: streaming stores; row chunks sized per direction
+    // (short for x, tall for y, medium for xy), shrunk until the grid keeps
+    // several workgroups per CU.
+    void default_layout() {
+        int rows = nwy == 1 ? 4 : (nwx == 1 ? 64 : 16);
+        const int W = 256 * vec_elems(dtype);
+        const long long strips = (a.nx + W - 1) / W;
+        const long long want = 8LL * device_cu_count();
+        while (rows > std::max(4, nwy) && strips * ((a.ny + rows - 1) / rows) < want) rows /= 2;
+        set_layout(rows, 1, 256, 1);
+        // explicit override "rows,order,threads,nt" for experiments
+        if (const char *env = getenv("MXS_STENCIL_TILE")) {
+            int r = 0, o = 0, t = 0, nt = 1;
+            const int k = sscanf(env, "%d,%d,%d,%d", &r, &o, &t, &nt);
+            if (k >= 3 && r > 0 && (o == 0 || o == 1) && (t == 64 || t == 128 || t == 256))
+                set_layout(r, o, t, nt != 0);
+        }
+    }
+
+    std::string key() const {
+        char buf[160];
+        snprintf(buf, sizeof buf, "s2d:%d:%d:%d:%d:%d:%lld:%d:%d", dtype, nwx, nwy, a.nx, a.ny, a.ld,
+                 a.periodic, a.ncoe > 0);
+        return buf;
+    }
+
+    mxs_status autotune(hipStream_t s) override;
+    void info(char *buf, int len) const override {
+        snprintf(buf, len, "stencil2d dtype=%d window=%dx%d rows=%d order=%d threads=%d nt_store=%d grid=%d",
+                 dtype, nwx, nwy, a.rows, a.order, threads, a.nt_store, a.nstrips * a.nchunks);
     }
 
     mxs_status set_io(const void *in, void *out) {
@@ -215,6 +247,54 @@ struct Stencil1DPlan final : mxs_plan_s {
     }
     mxs_status rebind(const void *in, void *out) override { return set_io(in, out); }
 };
+
+namespace {
+struct TunedLayout {
+    int rows, order, threads, nt;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TunedLayout> g_tuned;
+}  // namespace
+
+mxs_status Stencil2DPlan::autotune(hipStream_t s) {
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tuned.find(key());
+        if (it != g_tuned.end()) {
+            set_layout(it->second.rows, it->second.order, it->second.threads, it->second.nt);
+            return MXS_OK;
+        }
+    }
+    const TunedLayout start{a.rows, a.order, threads, a.nt_store};
+    TunedLayout best = start;
+    double best_t = 1e30;
+    const size_t lds_limit = static_cast<size_t>(device_lds_limit());
+    for (int rows : {2, 4, 8, 16, 32, 64, 128}) {
+        if (rows > 2 * a.ny && rows > 2) continue;
+        for (int nthreads : {256, 128}) {
+            if (stencil2d_lds_bytes(dtype, nwx, nwy, nthreads) > lds_limit) continue;
+            for (int order : {1, 0}) {
+                for (int nt : {1, 0}) {
+                    set_layout(rows, order, nthreads, nt);
+                    const double t = time_launches(
+                        [&] { return launch_stencil2d(dtype, nwx, nwy, a, threads, s); }, s, 2, 5);
+                    if (t < 0) {
+                        set_layout(start.rows, start.order, start.threads, start.nt);
+                        return hip_fail(hipGetLastError(), "autotune launch");
+                    }
+                    if (t < best_t) {
+                        best_t = t;
+                        best = TunedLayout{rows, order, nthreads, nt};
+                    }
+                }
+            }
+        }
+    }
+    set_layout(best.rows, best.order, best.threads, best.nt);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tuned[key()] = best;
+    return MXS_OK;
+}
 
 mxs_status check_coe(const double *coe, int ncoe) {
     if (ncoe < 0 || ncoe > kMaxCoe)
@@ -280,6 +360,7 @@ mxs_status mxs_create_2d(const mxs_stencil2d_desc *d, mxs_plan *plan) {
         delete p;
         return st;
     }
+    p->default_layout();
     if (stencil2d_lds_bytes(p->dtype, nwx, nwy, p->threads) > static_cast<size_t>(device_lds_limit())) {
         delete p;
         return fail(MXS_ERR_UNSUPPORTED, "window needs more LDS than the device offers");
@@ -291,7 +372,6 @@ mxs_status mxs_create_2d(const mxs_stencil2d_desc *d, mxs_plan *plan) {
         return hip_fail(e, "weights upload");
     }
     p->a.wts = p->wts.ptr;
-    p->layout();
     register_plan(p);
     *plan = p;
     return MXS_OK;
@@ -388,6 +468,18 @@ mxs_status mxs_swap(mxs_plan plan) {
 mxs_status mxs_set_io(mxs_plan plan, const void *in, void *out) {
     if (!plan || !is_live(plan)) return fail(MXS_ERR_BAD_HANDLE, "invalid plan");
     return plan->rebind(in, out);
+}
+
+mxs_status mxs_autotune(mxs_plan plan, void *hip_stream) {
+    if (!plan || !is_live(plan)) return fail(MXS_ERR_BAD_HANDLE, "invalid plan");
+    return plan->autotune(static_cast<hipStream_t>(hip_stream));
+}
+
+mxs_status mxs_plan_info(mxs_plan plan, char *buf, int len) {
+    if (!plan || !is_live(plan)) return fail(MXS_ERR_BAD_HANDLE, "invalid plan");
+    if (!buf || len <= 0) return fail(MXS_ERR_INVALID_ARG, "need a buffer");
+    plan->info(buf, len);
+    return MXS_OK;
 }
 
 mxs_status mxs_destroy(mxs_plan plan) {

@@ -87,6 +87,30 @@ __device__ __forceinline__ void store_vec<bf16>(bf16 *p, const float *x) {
     *reinterpret_cast<uint2 *>(p) = v;
 }
 
+// Streaming (non-temporal) vector stores: the line is written without being
+// kept in the caches, leaving L2 to the inputs that are read again.
+typedef double v2d_t __attribute__((ext_vector_type(2)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u_t __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ void store_vec_nt(T *p, const typename St<T>::acc *x);
+template <>
+__device__ __forceinline__ void store_vec_nt<double>(double *p, const double *x) {
+    v2d_t v = {x[0], x[1]};
+    __builtin_nontemporal_store(v, reinterpret_cast<v2d_t *>(p));
+}
+template <>
+__device__ __forceinline__ void store_vec_nt<float>(float *p, const float *x) {
+    v4f_t v = {x[0], x[1], x[2], x[3]};
+    __builtin_nontemporal_store(v, reinterpret_cast<v4f_t *>(p));
+}
+template <>
+__device__ __forceinline__ void store_vec_nt<bf16>(bf16 *p, const float *x) {
+    v2u_t v = {static_cast<uint32_t>(float_to_bf16(x[0])) | (static_cast<uint32_t>(float_to_bf16(x[1])) << 16),
+               static_cast<uint32_t>(float_to_bf16(x[2])) | (static_cast<uint32_t>(float_to_bf16(x[3])) << 16)};
+    __builtin_nontemporal_store(v, reinterpret_cast<v2u_t *>(p));
+}
+
 __device__ __forceinline__ long long wrap_ll(long long k, long long n) {
     long long r = k % n;
     return r < 0 ? r + n : r;
@@ -132,6 +156,9 @@ struct Stencil2DArgs {
     int nchunks;            // row chunks per strip
     int nstrips;            // column strips
     int vec_ok;             // 16-byte (8-byte for bf16) aligned rows
+    int order;              // tile order: 0 = each XCD a contiguous run of row chunks
+                            // of one strip; 1 = row-major sweep (strips fastest)
+    int nt_store;           // 1: non-temporal output stores
 };
 
 struct Stencil1DArgs {

@@ -15,6 +15,8 @@ struct mxs_plan_s {
     virtual mxs_status compute(hipStream_t) { return MXS_ERR_BAD_HANDLE; }
     virtual mxs_status swap() { return MXS_ERR_BAD_HANDLE; }
     virtual mxs_status rebind(const void *, void *) { return MXS_ERR_BAD_HANDLE; }
+    virtual mxs_status autotune(hipStream_t) { return MXS_OK; }
+    virtual void info(char *buf, int len) const;
 };
 
 namespace mxs {
@@ -46,5 +48,30 @@ size_t grid_bytes(int nx, int ny, long long ld, int dtype);
 int device_lds_limit();
 int device_cu_count();
 bool valid_dtype(int d);
+
+// Average time in seconds of `reps` calls of fn on stream s (after `warm`
+// untimed calls); negative on a launch error.
+template <class F> double time_launches(F &&fn, hipStream_t s, int warm, int reps) {
+    for (int i = 0; i < warm; ++i)
+        if (fn() != hipSuccess) return -1.0;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.0;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.0;
+    }
+    double r = -1.0;
+    if (hipEventRecord(e0, s) == hipSuccess) {
+        bool ok = true;
+        for (int i = 0; i < reps && ok; ++i) ok = fn() == hipSuccess;
+        float ms = 0;
+        if (ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+            hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+            r = ms * 1e-3 / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return r;
+}
 
 }  // namespace mxs

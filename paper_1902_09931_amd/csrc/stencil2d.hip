@@ -70,9 +70,15 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
     const int t = threadIdx.x;
     const int W = nt * V;
     const int rowlen = PAD + W + PAD;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int strip = tile / a.nchunks;
-    const int chunk = tile - strip * a.nchunks;
+    int strip, chunk;
+    if (a.order == 0) {
+        const int tile = xcd_tile(blockIdx.x, gridDim.x);
+        strip = tile / a.nchunks;
+        chunk = tile - strip * a.nchunks;
+    } else {
+        chunk = blockIdx.x / a.nstrips;
+        strip = blockIdx.x - chunk * a.nstrips;
+    }
     const long long i0 = static_cast<long long>(strip) * W;
     const int j0 = chunk * a.rows;
     const int H = min(a.rows, a.ny - j0);
@@ -88,9 +94,12 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
 #pragma unroll
         for (int v = 0; v < V; ++v) acc[q][v] = A(0);
 
-    for (int s0 = 0; s0 < niter; s0 += G) {
-        // ---- load G input rows (V elements per thread) ------------------
-        A xin[G][V];
+    // Halo values per stage: G rows x 2*PAD columns, at most HPT per thread.
+    constexpr int HPT = (G * 2 * PAD + 63) / 64;
+    const int hcount = G * 2 * PAD;
+
+    // Issue the loads of stage s0 (main vectors and halo values) into registers.
+    auto load_stage = [&](int s0, A (&xin)[G][V], A (&hv)[HPT > 0 ? HPT : 1]) {
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int s = s0 + u;
@@ -106,84 +115,109 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
 #pragma unroll
                     for (int v = 0; v < V; ++v) xin[u][v] = load_elem<T>(rowp, ib + v, a.nx, periodic);
                 }
-                if (a.ncoe) {
-#pragma unroll
-                    for (int v = 0; v < V; ++v) xin[u][v] = point_fun<A>(xin[u][v], coe, a.ncoe);
-                }
             } else {
 #pragma unroll
                 for (int v = 0; v < V; ++v) xin[u][v] = A(0);
             }
         }
-
-        // ---- stage the rows and their x halo in LDS ----------------------
         if constexpr (NWX > 1) {
-            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < HPT; ++q) {
+                const int h = t + q * nt;
+                A val = A(0);
+                if (h < hcount) {
+                    const int u = h / (2 * PAD);
+                    const int hh = h - u * 2 * PAD;
+                    const long long c = hh < PAD ? i0 - PAD + hh : i0 + W + (hh - PAD);
+                    const int s = s0 + u;
+                    long long r = static_cast<long long>(j0) - a.T + s;
+                    bool rv = s < niter;
+                    if (periodic) r = wrap_ll(r, a.ny);
+                    else rv = rv && r >= 0 && r < a.ny;
+                    if (rv) val = load_elem<T>(in + r * a.ld, c, a.nx, periodic);
+                }
+                hv[q] = val;
+            }
+        }
+    };
+
+    // acc[k] holds output row s - (NWY-1) + k; input row s meets it with
+    // window row NWY-1-k.  After the row, acc[0] is complete: it is written
+    // and the window shifts by one row.
+    auto consume = [&](const A *x, int s) {
+#pragma unroll
+        for (int k = 0; k < NWY; ++k) {
+#pragma unroll
+            for (int p = 0; p < NWX; ++p) {
+                const A wt = w[(NWY - 1 - k) * NWX + p];
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[k][v] = fma(wt, x[v + p], acc[k][v]);
+            }
+        }
+        const int jj = s - (NWY - 1);
+        if (jj >= 0 && jj < H) {
+            const int j = j0 + jj;
+            if (periodic || (j >= a.T && j <= a.ny - 1 - a.B)) {
+                T *rowp = out + static_cast<long long>(j) * a.ld;
+                if (store_vec_ok) {
+                    if (a.nt_store) store_vec_nt<T>(rowp + ib, acc[0]);
+                    else store_vec<T>(rowp + ib, acc[0]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const long long c = ib + v;
+                        if (c < a.nx && (periodic || (c >= a.L && c <= a.nx - 1 - a.R)))
+                            rowp[c] = from_acc<T>(acc[0][v]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k + 1 < NWY; ++k)
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[k][v] = acc[k + 1][v];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[NWY - 1][v] = A(0);
+    };
+
+    A cur[G][V], nxt[G][V];
+    A hcur[HPT > 0 ? HPT : 1], hnxt[HPT > 0 ? HPT : 1];
+    load_stage(0, cur, hcur);
+
+    for (int s0 = 0; s0 < niter; s0 += G) {
+        // the point function is applied once per loaded element
+        if (a.ncoe) {
+#pragma unroll
+            for (int u = 0; u < G; ++u)
+#pragma unroll
+                for (int v = 0; v < V; ++v) cur[u][v] = point_fun<A>(cur[u][v], coe, a.ncoe);
+            if constexpr (NWX > 1) {
+#pragma unroll
+                for (int q = 0; q < HPT; ++q) hcur[q] = point_fun<A>(hcur[q], coe, a.ncoe);
+            }
+        }
+        if constexpr (NWX > 1) {
+            __syncthreads();   // the previous stage's LDS reads are done
 #pragma unroll
             for (int u = 0; u < G; ++u) {
                 A *dst = lds + u * rowlen + PAD + t * V;
 #pragma unroll
-                for (int v = 0; v < V; ++v) dst[v] = xin[u][v];
+                for (int v = 0; v < V; ++v) dst[v] = cur[u][v];
             }
-            for (int h = t; h < G * 2 * PAD; h += nt) {
-                const int u = h / (2 * PAD);
-                const int hh = h - u * 2 * PAD;
-                const long long c = hh < PAD ? i0 - PAD + hh : i0 + W + (hh - PAD);
-                const int s = s0 + u;
-                long long r = static_cast<long long>(j0) - a.T + s;
-                bool rv = s < niter;
-                if (periodic) r = wrap_ll(r, a.ny);
-                else rv = rv && r >= 0 && r < a.ny;
-                A val = A(0);
-                if (rv) {
-                    val = load_elem<T>(in + r * a.ld, c, a.nx, periodic);
-                    if (a.ncoe) val = point_fun<A>(val, coe, a.ncoe);
+#pragma unroll
+            for (int q = 0; q < HPT; ++q) {
+                const int h = t + q * nt;
+                if (h < hcount) {
+                    const int u = h / (2 * PAD);
+                    const int hh = h - u * 2 * PAD;
+                    lds[u * rowlen + (hh < PAD ? hh : W + hh)] = hcur[q];
                 }
-                lds[u * rowlen + (hh < PAD ? hh : W + hh)] = val;
             }
-            __syncthreads();
         }
-
-        // ---- accumulate and emit completed rows ----------------------------
-        // acc[k] holds output row s - (NWY-1) + k; input row s meets it with
-        // window row NWY-1-k.  After the row, acc[0] is complete: it is
-        // written and the window shifts by one row.
-        auto consume = [&](const A *x, int s) {
-#pragma unroll
-            for (int k = 0; k < NWY; ++k) {
-#pragma unroll
-                for (int p = 0; p < NWX; ++p) {
-                    const A wt = w[(NWY - 1 - k) * NWX + p];
-#pragma unroll
-                    for (int v = 0; v < V; ++v) acc[k][v] = fma(wt, x[v + p], acc[k][v]);
-                }
-            }
-            const int jj = s - (NWY - 1);
-            if (jj >= 0 && jj < H) {
-                const int j = j0 + jj;
-                if (periodic || (j >= a.T && j <= a.ny - 1 - a.B)) {
-                    T *rowp = out + static_cast<long long>(j) * a.ld;
-                    if (store_vec_ok) {
-                        store_vec<T>(rowp + ib, acc[0]);
-                    } else {
-#pragma unroll
-                        for (int v = 0; v < V; ++v) {
-                            const long long c = ib + v;
-                            if (c < a.nx && (periodic || (c >= a.L && c <= a.nx - 1 - a.R)))
-                                rowp[c] = from_acc<T>(acc[0][v]);
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k + 1 < NWY; ++k)
-#pragma unroll
-                for (int v = 0; v < V; ++v) acc[k][v] = acc[k + 1][v];
-#pragma unroll
-            for (int v = 0; v < V; ++v) acc[NWY - 1][v] = A(0);
-        };
-
+        // next stage's loads overlap this stage's arithmetic
+        if (s0 + G < niter) load_stage(s0 + G, nxt, hnxt);
         if constexpr (NWX > 1) {
+            __syncthreads();
             const int nu = min(G, niter - s0);
 #pragma unroll 1
             for (int u = 0; u < nu; ++u) {
@@ -196,8 +230,14 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
         } else {
 #pragma unroll
             for (int u = 0; u < G; ++u)
-                if (s0 + u < niter) consume(xin[u], s0 + u);
+                if (s0 + u < niter) consume(cur[u], s0 + u);
         }
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+#pragma unroll
+            for (int v = 0; v < V; ++v) cur[u][v] = nxt[u][v];
+#pragma unroll
+        for (int q = 0; q < (HPT > 0 ? HPT : 1); ++q) hcur[q] = hnxt[q];
     }
 }
 

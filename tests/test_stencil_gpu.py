@@ -253,3 +253,44 @@ def test_stencil1d_full_batch(dt):
     else:
         s_abs = oracle.stencil1d_batch(np.abs(vv), offs, 2, 2, np.abs(w), True)
         assert np.all(np.abs(got - ref) <= stencil_bound(dt, s_abs, ref, 5, 0))
+
+
+# --- launch layouts -------------------------------------------------------------
+
+LAYOUTS = ["2,1,256,1", "4,0,256,0", "8,1,128,1", "16,0,128,0", "64,1,256,1", "128,0,256,1",
+           "3,1,64,0"]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("direction,ext", [("X", (2, 2, 0, 0)), ("Y", (0, 0, 2, 1)),
+                                           ("XY", (1, 2, 2, 1))])
+def test_every_layout_keeps_parity(monkeypatch, layout, direction, ext):
+    """Rows per workgroup, tile order, threads per workgroup and streaming
+    stores change only the schedule: every layout matches the oracle."""
+    monkeypatch.setenv("MXS_STENCIL_TILE", layout)
+    L, R, T, B = ext
+    rng = np.random.default_rng(17)
+    u = rng.uniform(-1, 1, (150, 1100))
+    w = rng.uniform(-1, 1, (T + B + 1) * (L + R + 1))
+    for periodic in (True, False):
+        got = run_2d(u, direction, periodic, ext, w, None, "f64")
+        check_against_oracle(u, got, direction, periodic, ext, w, None, "f64")
+
+
+def test_autotune_keeps_parity_and_reports_layout():
+    rng = np.random.default_rng(18)
+    u = rng.uniform(-1, 1, (300, 700))
+    w = rng.uniform(-1, 1, 9)
+    din = to_device(u, "f32")
+    dout = torch.full_like(din, float("nan"))
+    p = b.mxs_create_2d(700, 300, 700, b.MXS_XY, b.MXS_NP, b.MXS_F32, 1, 1, 1, 1, w, None, din, dout)
+    try:
+        b.mxs_autotune(p)
+        info = b.mxs_plan_info(p)
+        assert "rows=" in info and "threads=" in info
+        dout.fill_(float("nan"))
+        b.mxs_compute(p)
+        torch.cuda.synchronize()
+    finally:
+        b.mxs_destroy(p)
+    check_against_oracle(u, to_host(dout), "XY", False, (1, 1, 1, 1), w, None, "f32")
