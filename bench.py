@@ -138,11 +138,13 @@ def bench_cyclic_tri(torch, b, wl, dt, steps, warmup):
     r = torch.from_numpy(np.random.default_rng(5).uniform(-1, 1, total)).to(tdt).cuda()
     x = torch.empty_like(r)
     p = b.mxs_create_cyclic_solve(1, [2.5, -1.0], b.MXS_LINES_RAGGED, 0, 0, 0, offs, code, r, x)
+    b.mxs_autotune(p)
+    layout = b.mxs_plan_info(p)
     sec, _ = time_loop(torch, lambda: b.mxs_compute(p), steps, warmup)
     b.mxs_destroy(p)
     per = sec / steps
     nbytes = 2 * total * r.element_size()
-    return {"points": total, "lines": int(len(lengths)), "s_per_pass": per,
+    return {"points": total, "lines": int(len(lengths)), "s_per_pass": per, "layout": layout,
             "gpoints_per_s": total / per / 1e9, "gb_per_s": nbytes / per / 1e9,
             "frac_hbm_peak": nbytes / per / 1e9 / HBM_PEAK_GBS}
 
@@ -159,12 +161,14 @@ def bench_ch(torch, b, wl, n, steps, warmup):
     dx = 2 * math.pi / n
     bufs = ch_buffers(torch, c0, torch.float64)
     p = b.mxs_ch_create(n, n, dx, dx, 0.1 * dx * dx, 1.0, 0.01, b.MXS_F64, *bufs)
+    b.mxs_autotune(p)
+    layout = b.mxs_plan_info(p)
     sec, _ = time_loop(torch, lambda: b.mxs_ch_step(p, 1, True), steps, warmup)
     m = b.mxs_ch_mass(p)[0]
     b.mxs_destroy(p)
     per = sec / steps
     floor = 56 * n * n
-    return {"steps_timed": steps, "s_per_step": per, "steps_per_s": 1.0 / per,
+    return {"steps_timed": steps, "s_per_step": per, "steps_per_s": 1.0 / per, "layout": layout,
             "floor_bytes_per_step": floor, "gb_per_s_at_floor": floor / per / 1e9,
             "frac_hbm_peak_at_floor": floor / per / 1e9 / HBM_PEAK_GBS,
             "mass_drift": abs(m - float(c0.sum())) / float(abs(c0).sum())}
@@ -186,6 +190,8 @@ def bench_ensemble(torch, b, wl, steps, warmup):
         bufs = [ch_buffers(torch, c0, tdt) for c0 in c0s]
         p = b.mxs_ch_ensemble_create(sizes, sizes, dxs, dxs, dts, 1.0, 0.01, code,
                                      [q[0] for q in bufs], [q[1] for q in bufs], [q[2] for q in bufs])
+        b.mxs_autotune(p)
+        out[f"ensemble_{name}_layout"] = b.mxs_plan_info(p)
         sec, _ = time_loop(torch, lambda: b.mxs_ch_step(p, 1, True), steps, warmup)
         b.mxs_destroy(p)
         out[f"ensemble_{name}_steps_per_s"] = steps / sec
@@ -193,6 +199,8 @@ def bench_ensemble(torch, b, wl, steps, warmup):
     bufs = [ch_buffers(torch, c0, torch.float64) for c0 in c0s]
     plans = [b.mxs_ch_create(n, n, d, d, t, 1.0, 0.01, b.MXS_F64, *q)
              for n, d, t, q in zip(sizes, dxs, dts, bufs)]
+    for p in plans:
+        b.mxs_autotune(p)
 
     def seq_step():
         for p in plans:

@@ -66,53 +66,75 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
 #pragma unroll
         for (int v = 0; v < V; ++v) acc[k][v] = A(0);
 
-    for (int s0 = 0; s0 < niter; s0 += G) {
-        A cb[G][V], fc[G][V], df[G][V];
+    // halo columns per stage: G rows x 2*PAD, at most HPT per thread
+    constexpr int HPT = (G * 2 * PAD + kRhsThreads - 1) / kRhsThreads;
+    const int hcount = G * 2 * PAD;
+
+    // issue the loads of C^n and C^{n-1} for the G input rows of stage s0
+    auto load_stage = [&](int s0, A (&c)[G][V], A (&p)[G][V], A (&hc)[HPT], A (&hp)[HPT]) {
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int r = static_cast<int>(wrap_ll(j0 - 2 + s0 + u, ny));
             const T *cr = cur + static_cast<long long>(r) * nx;
             const T *pr = prev + static_cast<long long>(r) * nx;
-            A c[V], p[V];
             if (full_vec) {
-                load_vec<T>(cr + ib, c);
-                load_vec<T>(pr + ib, p);
+                load_vec<T>(cr + ib, c[u]);
+                load_vec<T>(pr + ib, p[u]);
             } else {
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     const int col = static_cast<int>(wrap_ll(ib + v, nx));
-                    c[v] = to_acc<T>(cr[col]);
-                    p[v] = to_acc<T>(pr[col]);
+                    c[u][v] = to_acc<T>(cr[col]);
+                    p[u][v] = to_acc<T>(pr[col]);
                 }
             }
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                cb[u][v] = A(2) * c[v] - p[v];
-                fc[u][v] = c[v] * c[v] * c[v] - c[v];
-                df[u][v] = c[v] - p[v];
-            }
         }
-        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < HPT; ++q) {
+            const int h = t + q * nt;
+            A vc = A(0), vp = A(0);
+            if (h < hcount) {
+                const int u = h / (2 * PAD);
+                const int hh = h - u * 2 * PAD;
+                const int r = static_cast<int>(wrap_ll(j0 - 2 + s0 + u, ny));
+                const long long col = hh < PAD ? static_cast<long long>(i0) - PAD + hh
+                                               : static_cast<long long>(i0) + W + (hh - PAD);
+                const long long o = static_cast<long long>(r) * nx + wrap_ll(col, nx);
+                vc = to_acc<T>(cur[o]);
+                vp = to_acc<T>(prev[o]);
+            }
+            hc[q] = vc;
+            hp[q] = vp;
+        }
+    };
+
+    A c0[G][V], p0[G][V], c1[G][V], p1[G][V], hc0[HPT], hp0[HPT], hc1[HPT], hp1[HPT];
+    load_stage(0, c0, p0, hc0, hp0);
+
+    for (int s0 = 0; s0 < niter; s0 += G) {
+        __syncthreads();   // the previous stage's LDS reads are done
 #pragma unroll
         for (int u = 0; u < G; ++u)
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                lcb[u * rowlen + PAD + t * V + v] = cb[u][v];
-                lfc[u * rowlen + PAD + t * V + v] = fc[u][v];
+                const A c = c0[u][v], p = p0[u][v];
+                lcb[u * rowlen + PAD + t * V + v] = A(2) * c - p;
+                lfc[u * rowlen + PAD + t * V + v] = c * c * c - c;
             }
-        for (int h = t; h < G * 2 * PAD; h += nt) {
-            const int u = h / (2 * PAD);
-            const int hh = h - u * 2 * PAD;
-            const int r = static_cast<int>(wrap_ll(j0 - 2 + s0 + u, ny));
-            const long long col = hh < PAD ? static_cast<long long>(i0) - PAD + hh
-                                           : static_cast<long long>(i0) + W + (hh - PAD);
-            const int cc = static_cast<int>(wrap_ll(col, nx));
-            const A c = to_acc<T>(cur[static_cast<long long>(r) * nx + cc]);
-            const A p = to_acc<T>(prev[static_cast<long long>(r) * nx + cc]);
-            const int pos = u * rowlen + (hh < PAD ? hh : W + hh);
-            lcb[pos] = A(2) * c - p;
-            lfc[pos] = c * c * c - c;
+#pragma unroll
+        for (int q = 0; q < HPT; ++q) {
+            const int h = t + q * nt;
+            if (h < hcount) {
+                const int u = h / (2 * PAD);
+                const int hh = h - u * 2 * PAD;
+                const int pos = u * rowlen + (hh < PAD ? hh : W + hh);
+                const A c = hc0[q], p = hp0[q];
+                lcb[pos] = A(2) * c - p;
+                lfc[pos] = c * c * c - c;
+            }
         }
+        // the next stage's loads overlap this stage's arithmetic
+        if (s0 + G < niter) load_stage(s0 + G, c1, p1, hc1, hp1);
         __syncthreads();
 
 #pragma unroll
@@ -150,13 +172,13 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
                     }
                 }
 #pragma unroll
-                for (int v = 0; v < V; ++v) acc[2][v] = fma(cdiff, df[u][v], acc[2][v]);
+                for (int v = 0; v < V; ++v) acc[2][v] = fma(cdiff, c0[u][v] - p0[u][v], acc[2][v]);
 
                 const int jj = s - 4;
                 if (jj >= 0 && jj < H) {
                     TW *rowp = R + static_cast<long long>(j0 + jj) * nx;
                     if (full_vec) {
-                        store_vec<TW>(rowp + ib, acc[0]);
+                        store_vec_nt<TW>(rowp + ib, acc[0]);
                     } else {
 #pragma unroll
                         for (int v = 0; v < V; ++v)
@@ -170,6 +192,18 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
 #pragma unroll
                 for (int v = 0; v < V; ++v) acc[4][v] = A(0);
             }
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                c0[u][v] = c1[u][v];
+                p0[u][v] = p1[u][v];
+            }
+#pragma unroll
+        for (int q = 0; q < HPT; ++q) {
+            hc0[q] = hc1[q];
+            hp0[q] = hp1[q];
         }
     }
 }

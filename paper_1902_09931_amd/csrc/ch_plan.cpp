@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <vector>
 
 namespace mxs {
@@ -71,7 +72,8 @@ struct CHPlan final : mxs_plan_s {
     DevBuf rhs_d[3], rows_d, cols_d[3], mass_d[3];
     DevBuf partial, mass_out;
     double *mass_host = nullptr;
-    int rhs_blocks = 0, row_lines = 0, row_grid = 1, colsAC = 0, colsB = 0, mass_blocks = 0;
+    int rhs_blocks = 0, rhs_rows = 16, row_lines = 0, row_grid = 1, row_nw = 1, colsAC = 0, colsB = 0,
+        mass_blocks = 0, max_nx = 0;
     size_t row_lds = 0;
 
     hipStream_t cap = nullptr;
@@ -79,8 +81,7 @@ struct CHPlan final : mxs_plan_s {
 
     CHPlan() : mxs_plan_s(KIND_CH) {}
     ~CHPlan() override {
-        for (auto &e : exec)
-            if (e) (void)hipGraphExecDestroy(e);
+        drop_graphs();
         if (cap) (void)hipStreamDestroy(cap);
         if (mass_host) (void)hipHostFree(mass_host);
     }
@@ -92,7 +93,7 @@ struct CHPlan final : mxs_plan_s {
                                      rhs_blocks, s);
         if (e != hipSuccess) return e;
         e = launch_rows(wdtype, 2, static_cast<const RowsInst *>(rows_d.ptr), ninst(), row_lines,
-                        row_grid, row_lds, s);
+                        row_nw, row_grid, row_lds, s);
         if (e != hipSuccess) return e;
         return launch_cols(wdtype, dtype, 2, 1, static_cast<const ColsInst *>(cols_d[r].ptr),
                            ninst(), colsAC, colsB, s);
@@ -151,20 +152,25 @@ struct CHPlan final : mxs_plan_s {
         return finite ? MXS_OK : fail(MXS_ERR_NONFINITE, "the mass is not finite");
     }
 
-    mxs_status build() {
+    // Right-hand side tables for row chunks of `rows` rows (0: pick a height
+    // that keeps several workgroups per CU).
+    mxs_status build_rhs(int rows) {
         const int n = ninst();
         const int cus = device_cu_count();
         const int Vs = dtype == F64 ? 2 : 4;
-        // right-hand side tables
-        int blk = 0, maxnx = 0;
-        long long total_tiles = 0;
-        for (const Inst &I : inst) total_tiles += (I.nx + kRhsThreads * Vs - 1) / (kRhsThreads * Vs) * ((I.ny + 63) / 64);
-        int rows = 64;
-        while (rows > 8 && total_tiles < 8LL * cus) {
-            rows /= 2;
-            total_tiles = 0;
-            for (const Inst &I : inst) total_tiles += (I.nx + kRhsThreads * Vs - 1) / (kRhsThreads * Vs) * ((I.ny + rows - 1) / rows);
+        auto tiles = [&](int r) {
+            long long t = 0;
+            for (const Inst &I : inst)
+                t += static_cast<long long>((I.nx + kRhsThreads * Vs - 1) / (kRhsThreads * Vs)) *
+                     ((I.ny + r - 1) / r);
+            return t;
+        };
+        if (rows <= 0) {
+            rows = 16;
+            while (rows > 4 && tiles(rows) < 8LL * cus) rows /= 2;
         }
+        rhs_rows = rows;
+        int blk = 0;
         for (int r = 0; r < 3; ++r) rhs_h[r].resize(n);
         for (int g = 0; g < n; ++g) {
             const Inst &I = inst[g];
@@ -197,9 +203,67 @@ struct CHPlan final : mxs_plan_s {
                 rr.cur = I.buf[(r + 1) % 3];
                 rhs_h[r][g] = rr;
             }
-            maxnx = std::max(maxnx, I.nx);
         }
         rhs_blocks = blk;
+        hipError_t e = hipSuccess;
+        for (int r = 0; r < 3 && e == hipSuccess; ++r)
+            e = rhs_d[r].upload(rhs_h[r].data(), sizeof(RhsInst) * n);
+        return e == hipSuccess ? MXS_OK : hip_fail(e, "plan tables upload");
+    }
+
+    void set_row_waves(int w) {
+        row_nw = w;
+        row_lds = line_lds_bytes(max_nx, row_nw);
+        row_grid = wave_grid(row_lines, row_lds);
+    }
+
+    void drop_graphs() {
+        for (auto &e : exec)
+            if (e) {
+                (void)hipGraphExecDestroy(e);
+                e = nullptr;
+            }
+    }
+
+    // Chooses the right-hand side chunk height and the wavefronts per row
+    // solve by timing whole steps.  The timed steps rewrite only the buffer
+    // that the next step overwrites anyway (C^{n+1}) and the plan's scratch,
+    // and do not advance the step count.
+    mxs_status autotune(hipStream_t s) override {
+        const int r = static_cast<int>(steps % 3);
+        int best_rows = rhs_rows, best_w = row_nw;
+        double best_t = 1e30;
+        for (int rows : {4, 8, 16, 32}) {
+            mxs_status st = build_rhs(rows);
+            if (st) return st;
+            for (int w : {1, 2, 4}) {
+                if (line_lds_bytes(max_nx, w) > static_cast<size_t>(device_lds_limit())) continue;
+                set_row_waves(w);
+                const double t = time_launches([&] { return enqueue(r, s); }, s, 1, 3);
+                if (t < 0) return hip_fail(hipGetLastError(), "autotune launch");
+                if (t < best_t) {
+                    best_t = t;
+                    best_rows = rows;
+                    best_w = w;
+                }
+            }
+        }
+        set_row_waves(best_w);
+        drop_graphs();
+        return build_rhs(best_rows);
+    }
+
+    void info(char *buf, int len) const override {
+        snprintf(buf, len, "ch instances=%d dtype=%d rhs_rows=%d rhs_blocks=%d row_waves=%d row_grid=%d cols_blocks=%d",
+                 ninst(), dtype, rhs_rows, rhs_blocks, row_nw, row_grid, colsAC);
+    }
+
+    mxs_status build() {
+        const int n = ninst();
+        int maxnx = 0;
+        for (const Inst &I : inst) maxnx = std::max(maxnx, I.nx);
+        mxs_status bst = build_rhs(0);
+        if (bst) return bst;
 
         // row solves (in place on w) and column solves (w -> C^{n+1})
         rows_h.resize(n);
@@ -236,7 +300,7 @@ struct CHPlan final : mxs_plan_s {
             co.blk0 = bAC;
             co.blkB0 = bB;
             bAC += co.nstrips * co.nseg;
-            bB += co.nstrips;
+            bB += (I.nx + kBCols - 1) / kBCols;
             hipError_t e = I.carry.alloc(sizeof(double) * 4 * static_cast<size_t>(I.nx) * co.nseg);
             if (e != hipSuccess) return hip_fail(e, "carry allocation");
             co.carry = static_cast<double *>(I.carry.ptr);
@@ -252,10 +316,10 @@ struct CHPlan final : mxs_plan_s {
         row_lines = line;
         colsAC = bAC;
         colsB = bB;
-        row_lds = wave_line_lds_bytes(wave_chunk(maxnx));
+        max_nx = maxnx;
+        set_row_waves(line_waves(maxnx));
         if (row_lds > static_cast<size_t>(device_lds_limit()))
             return fail(MXS_ERR_UNSUPPORTED, "rows too long for the LDS of one workgroup");
-        row_grid = wave_grid(row_lines, row_lds);
 
         // mass
         int mb = 0;
@@ -277,8 +341,7 @@ struct CHPlan final : mxs_plan_s {
 
         hipError_t e = hipSuccess;
         for (int r = 0; r < 3 && e == hipSuccess; ++r) {
-            e = rhs_d[r].upload(rhs_h[r].data(), sizeof(RhsInst) * n);
-            if (e == hipSuccess) e = cols_d[r].upload(cols_h[r].data(), sizeof(ColsInst) * n);
+            e = cols_d[r].upload(cols_h[r].data(), sizeof(ColsInst) * n);
             if (e == hipSuccess) e = mass_d[r].upload(mass_h[r].data(), sizeof(MassInst) * n);
         }
         if (e == hipSuccess) e = rows_d.upload(rows_h.data(), sizeof(RowsInst) * n);

@@ -3,14 +3,16 @@
 // in solve.h.  All elimination arithmetic is double.
 //
 // Contiguous lines (rows of a grid, or uneven lines stored back to back) go
-// one line per wavefront.  The line is copied into LDS; lane l owns the k
-// consecutive elements of chunk l.  Each cyclic recurrence is then
-//   1. a local pass: every lane runs the recurrence over its chunk from a
+// one line per workgroup of one or four wavefronts.  The line is copied into
+// LDS with coalesced loads (16 in flight per thread); thread t owns the k
+// consecutive elements of chunk t.  Each cyclic recurrence is then
+//   1. a local pass: every thread runs the recurrence over its chunk from a
 //      zero state, giving the affine map state_out = M^len state_in + e;
-//   2. an inclusive scan of these affine maps across the 64 lanes with
-//      cross-lane shuffles, whose total gives the wrap-around closure
+//   2. an inclusive scan of these affine maps: across the 64 lanes of a
+//      wavefront with cross-lane shuffles, then across the wavefronts
+//      through LDS; the total gives the wrap-around closure
 //      state_-1 = (I - M^n)^-1 e_total;
-//   3. a final pass from each lane's true incoming state.
+//   3. a final pass from each thread's true incoming state.
 // The backward recurrence is the same with the index order reversed.
 //
 // Columns of a grid go in three phases over segments of kSeg rows, one lane
@@ -114,52 +116,24 @@ __device__ __forceinline__ void companion_pow(double p1, double p2, int len, Aff
     m.a = ra; m.b = rb; m.c = rc; m.d = rd;
 }
 
-// One cyclic recurrence y_i = b_i + p1 y_{i-1} + p2 y_{i-2} over a line held in
-// LDS in place (REV: the index order reversed, i.e. the backward recurrence).
-template <int BW, bool REV>
-__device__ void wave_cyclic_pass(double *line, int n, int k, double p1, double p2) {
-    const int lane = threadIdx.x & 63;
-    const int start = min(lane * k, n);
-    const int len = min(start + k, n) - start;
-    double *base = line + lane * (k + 1);
+__device__ __forceinline__ Aff aff_identity() {
+    Aff r;
+    r.a = 1.0; r.b = 0.0; r.c = 0.0; r.d = 1.0; r.e0 = 0.0; r.e1 = 0.0;
+    return r;
+}
 
-    double s0 = 0.0, s1 = 0.0;
-    for (int q = 0; q < len; ++q) {
-        const int j = REV ? len - 1 - q : q;
-        const double y = BW == 2 ? fma(p2, s1, fma(p1, s0, base[j])) : fma(p1, s0, base[j]);
-        s1 = s0;
-        s0 = y;
-    }
-    Aff m;
-    companion_pow(p1, BW == 2 ? p2 : 0.0, len, m);
-    m.e0 = s0;
-    m.e1 = s1;
+// One step of the recurrence y = b + p1 s0 + p2 s1; the p2 term does not
+// depend on the previous step, so the dependent chain is one FMA long.
+template <int BW> __device__ __forceinline__ double rec_step(double b, double s0, double s1,
+                                                            double p1, double p2) {
+    return BW == 2 ? fma(p1, s0, fma(p2, s1, b)) : fma(p1, s0, b);
+}
 
-    // inclusive scan in processing order (lanes ascending, or descending for REV)
-    Aff inc = m;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const Aff o = shfl_aff<!REV>(inc, d);
-        if (REV ? lane + d < 64 : lane >= d) inc = compose(inc, o);
-    }
-    const Aff tot = bcast_aff(inc, REV ? 0 : 63);
-    // wrap-around closure: state before the first element = (I - T)^-1 e
-    const double ia = 1.0 - tot.a, ib = -tot.b, ic = -tot.c, id = 1.0 - tot.d;
-    const double det = ia * id - ib * ic;
-    const double x0 = (id * tot.e0 - ib * tot.e1) / det;
-    const double x1 = (ia * tot.e1 - ic * tot.e0) / det;
-    const Aff pre = shfl_aff<!REV>(inc, 1);
-    const bool first = REV ? lane == 63 : lane == 0;
-    s0 = first ? x0 : pre.a * x0 + pre.b * x1 + pre.e0;
-    s1 = first ? x1 : pre.c * x0 + pre.d * x1 + pre.e1;
-
-    for (int q = 0; q < len; ++q) {
-        const int j = REV ? len - 1 - q : q;
-        const double y = BW == 2 ? fma(p2, s1, fma(p1, s0, base[j])) : fma(p1, s0, base[j]);
-        base[j] = y;
-        s1 = s0;
-        s0 = y;
-    }
+// Chunk length (even, so that chunk strides k + 1 are odd) of a line of n
+// elements spread over NT threads; chunk t is stored in LDS at t * (k + 1).
+template <int NT> __device__ __forceinline__ int chunk_len(int n) {
+    const int k = (n + 2 * NT - 1) / (2 * NT) * 2;
+    return k < 2 ? 2 : k;
 }
 
 __device__ __forceinline__ int lds_pos(int i, int k, float kinv) {
@@ -169,48 +143,184 @@ __device__ __forceinline__ int lds_pos(int i, int k, float kinv) {
     return c * (k + 1) + (i - c * k);
 }
 
-// Solve one contiguous line (in -> out, may alias) with the wavefront.
-template <typename TI, typename TO, int BW>
-__device__ void wave_solve_line(const TI *in, TO *out, int n, double p1, double p2, double invK,
-                                double *line) {
-    const int lane = threadIdx.x & 63;
-    const int k = static_cast<int>((n + 127) / 128 * 2 < 2 ? 2 : (n + 127) / 128 * 2);
-    const float kinv = 1.0f / static_cast<float>(k);
-    __syncthreads();
-    for (int i = lane; i < n; i += 64) line[lds_pos(i, k, kinv)] = to_f64<TI>(in[i]);
-    __syncthreads();
-    wave_cyclic_pass<BW, false>(line, n, k, p1, p2);
-    wave_cyclic_pass<BW, true>(line, n, k, p1, p2);
-    __syncthreads();
-    for (int i = lane; i < n; i += 64) out[i] = from_f64<TO>(line[lds_pos(i, k, kinv)] * invK);
-}
+// One cyclic recurrence over a line held in LDS, in place, by the NT = 64 NW
+// threads of the workgroup (REV: the index order reversed, i.e. the backward
+// recurrence).  xchg holds NW affine maps in LDS.
+template <int BW, int NW, bool REV>
+__device__ void block_cyclic_pass(double *line, int n, int k, double p1, double p2, Aff *xchg) {
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int start = min(t * k, n);
+    const int len = min(start + k, n) - start;
+    double *base = line + t * (k + 1);
 
-template <typename T, int BW>
-__global__ void __launch_bounds__(64) ragged_lines_kernel(const RaggedLines a) {
-    extern __shared__ double line[];
-    const T *in = static_cast<const T *>(a.in);
-    T *out = static_cast<T *>(a.out);
-    for (int li = blockIdx.x; li < a.nlines; li += gridDim.x) {
-        const int b = a.order[li];
-        const long long base = a.offsets[b];
-        const int n = static_cast<int>(a.offsets[b + 1] - base);
-        wave_solve_line<T, T, BW>(in + base, out + base, n, a.p1, a.p2, a.invK, line);
+    double s0 = 0.0, s1 = 0.0;
+    for (int q = 0; q < len; ++q) {
+        const int j = REV ? len - 1 - q : q;
+        const double y = rec_step<BW>(base[j], s0, s1, p1, p2);
+        s1 = s0;
+        s0 = y;
+    }
+    Aff m;
+    companion_pow(p1, BW == 2 ? p2 : 0.0, len, m);
+    m.e0 = s0;
+    m.e1 = s1;
+
+    // inclusive scan within the wavefront, in processing order
+    Aff inc = m;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const Aff o = shfl_aff<!REV>(inc, d);
+        if (REV ? lane + d < 64 : lane >= d) inc = compose(inc, o);
+    }
+    // maps of the earlier wavefronts (processing order) and of the whole line
+    Aff pre_wave = aff_identity(), tot;
+    if constexpr (NW > 1) {
+        if (REV ? lane == 0 : lane == 63) xchg[wave] = inc;
+        __syncthreads();
+        tot = aff_identity();
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            const int w = REV ? NW - 1 - q : q;
+            const Aff x = xchg[w];
+            if ((REV && w > wave) || (!REV && w < wave)) pre_wave = compose(x, pre_wave);
+            tot = compose(x, tot);
+        }
+        __syncthreads();
+    } else {
+        tot = bcast_aff(inc, REV ? 0 : 63);
+    }
+    // wrap-around closure: state before the first element = (I - T)^-1 e
+    const double ia = 1.0 - tot.a, ib = -tot.b, ic = -tot.c, id = 1.0 - tot.d;
+    const double det = ia * id - ib * ic;
+    const double x0 = (id * tot.e0 - ib * tot.e1) / det;
+    const double x1 = (ia * tot.e1 - ic * tot.e0) / det;
+    const Aff prev = shfl_aff<!REV>(inc, 1);
+    const Aff pre = (REV ? lane == 63 : lane == 0) ? pre_wave : compose(prev, pre_wave);
+    s0 = pre.a * x0 + pre.b * x1 + pre.e0;
+    s1 = pre.c * x0 + pre.d * x1 + pre.e1;
+
+    for (int q = 0; q < len; ++q) {
+        const int j = REV ? len - 1 - q : q;
+        const double y = rec_step<BW>(base[j], s0, s1, p1, p2);
+        base[j] = y;
+        s1 = s0;
+        s0 = y;
     }
 }
 
-template <typename T, int BW>
-__global__ void __launch_bounds__(64) rows_kernel(const RowsInst *__restrict__ inst, int ninst,
-                                                  int nlines) {
-    extern __shared__ double line[];
-    for (int li = blockIdx.x; li < nlines; li += gridDim.x) {
+// Contiguous lines solved by a persistent workgroup, one line at a time.
+// The first U * NT elements of the next line are loaded into registers while
+// the current line is being solved, so the copy into LDS rarely waits for
+// memory; longer lines load their remaining elements in further batches.
+// Src::get(li) describes line li: input, output, length and coefficients.
+struct LineRef {
+    const void *in;
+    void *out;
+    int n;
+    double p1, p2, invK;
+};
+
+template <typename TI, typename TO, int BW, int NW, class Src>
+__device__ void solve_lines(const Src &src, int nlines, double *smem) {
+    constexpr int NT = 64 * NW;
+    constexpr int U = 32;
+    const int t = threadIdx.x;
+    double r[U];
+    auto fetch = [&](const LineRef &L, int b0) {
+        const TI *in = static_cast<const TI *>(L.in);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = b0 + u * NT + t;
+            r[u] = i < L.n ? to_f64<TI>(in[i]) : 0.0;
+        }
+    };
+    int li = blockIdx.x;
+    LineRef L{};
+    if (li < nlines) {
+        L = src.get(li);
+        fetch(L, 0);
+    }
+    while (li < nlines) {
+        const int n = L.n;
+        const int k = chunk_len<NT>(n);
+        const float kinv = 1.0f / static_cast<float>(k);
+        double *line = smem;
+        Aff *xchg = reinterpret_cast<Aff *>(smem + NT * (k + 1));
+        __syncthreads();   // the previous line's LDS reads are done
+        for (int b0 = 0; b0 < n; b0 += U * NT) {
+            if (b0 > 0) fetch(L, b0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = b0 + u * NT + t;
+                if (i < n) line[lds_pos(i, k, kinv)] = r[u];
+            }
+        }
+        __syncthreads();
+        const int next = li + gridDim.x;
+        LineRef Ln{};
+        if (next < nlines) {
+            Ln = src.get(next);
+            fetch(Ln, 0);   // in flight while this line is solved
+        }
+        block_cyclic_pass<BW, NW, false>(line, n, k, L.p1, L.p2, xchg);
+        block_cyclic_pass<BW, NW, true>(line, n, k, L.p1, L.p2, xchg);
+        __syncthreads();
+        TO *out = static_cast<TO *>(L.out);
+        for (int i = t; i < n; i += NT) out[i] = from_f64<TO>(line[lds_pos(i, k, kinv)] * L.invK);
+        li = next;
+        L = Ln;
+    }
+}
+
+template <typename T>
+struct RaggedSrc {
+    RaggedLines a;
+    __device__ LineRef get(int li) const {
+        const int b = a.order[li];
+        const long long base = a.offsets[b];
+        LineRef L;
+        L.in = static_cast<const T *>(a.in) + base;
+        L.out = static_cast<T *>(a.out) + base;
+        L.n = static_cast<int>(a.offsets[b + 1] - base);
+        L.p1 = a.p1;
+        L.p2 = a.p2;
+        L.invK = a.invK;
+        return L;
+    }
+};
+
+template <typename T>
+struct RowsSrc {
+    const RowsInst *inst;
+    int ninst;
+    __device__ LineRef get(int li) const {
         int g = 0;
         while (g + 1 < ninst && inst[g + 1].line0 <= li) ++g;
         const RowsInst &I = inst[g];
         const long long j = li - I.line0;
-        const T *in = static_cast<const T *>(I.in) + j * I.ld;
-        T *out = static_cast<T *>(I.out) + j * I.ld;
-        wave_solve_line<T, T, BW>(in, out, I.nx, I.p1, I.p2, I.invK, line);
+        LineRef L;
+        L.in = static_cast<const T *>(I.in) + j * I.ld;
+        L.out = static_cast<T *>(I.out) + j * I.ld;
+        L.n = I.nx;
+        L.p1 = I.p1;
+        L.p2 = I.p2;
+        L.invK = I.invK;
+        return L;
     }
+};
+
+template <typename T, int BW, int NW>
+__global__ void __launch_bounds__(64 * NW) ragged_lines_kernel(const RaggedLines a) {
+    extern __shared__ double smem[];
+    solve_lines<T, T, BW, NW>(RaggedSrc<T>{a}, a.nlines, smem);
+}
+
+template <typename T, int BW, int NW>
+__global__ void __launch_bounds__(64 * NW) rows_kernel(const RowsInst *__restrict__ inst, int ninst,
+                                                       int nlines) {
+    extern __shared__ double smem[];
+    solve_lines<T, T, BW, NW>(RowsSrc<T>{inst, ninst}, nlines, smem);
 }
 
 // ---- columns -------------------------------------------------------------------
@@ -264,68 +374,167 @@ __global__ void __launch_bounds__(kColsThreads) cols_phase_a(const ColsInst *__r
     cy[3 * I.nx] = t1;
 }
 
+// Phase B: the segments of a column are split into kBGroups groups, one
+// thread each (a workgroup covers kBCols columns).  Each thread composes the
+// affine maps of its segments, the groups of a column combine their maps
+// through LDS (wrap-around closure included), and each thread then writes
+// the true incoming states of its own segments.  Summaries are loaded PB
+// segments at a time so that their loads are in flight together.
+constexpr int PB = 8;
+
+__device__ __forceinline__ void mat2_load(const double *m, Aff &x) {
+    x.a = m[0]; x.b = m[1]; x.c = m[2]; x.d = m[3];
+}
+
 template <int BW>
 __global__ void __launch_bounds__(kColsThreads) cols_phase_b(const ColsInst *__restrict__ inst,
                                                             int ninst) {
+    __shared__ Aff xa[kBGroups][kBCols];
     const int g = find_inst(inst, ninst, blockIdx.x, true);
     const ColsInst &I = inst[g];
-    const int i = (blockIdx.x - I.blkB0) * kColsThreads + threadIdx.x;
-    if (i >= I.nx) return;
+    const int cl = threadIdx.x % kBCols, q = threadIdx.x / kBCols;
+    const int col = (blockIdx.x - I.blkB0) * kBCols + cl;
+    const bool valid = col < I.nx;
     const long long nx = I.nx;
-    double *cy = I.carry + i;
+    double *cy = I.carry + (valid ? col : 0);
     const int ns = I.nseg;
+    const int sp = (ns + kBGroups - 1) / kBGroups;
+    const int sb = min(q * sp, ns), se = min(sb + sp, ns);
+    Aff Tf, Tl, Qf, Ql;
+    mat2_load(I.Tf, Tf);
+    mat2_load(I.Tl, Tl);
+    mat2_load(I.Qf, Qf);
+    mat2_load(I.Ql, Ql);
 
-    // forward: the end state from zero, then the closure and every incoming state
-    double c0 = 0.0, c1 = 0.0;
-    for (int s = 0; s < ns; ++s) {
-        const double *T = s == ns - 1 ? I.Tl : I.Tf;
-        const double e0 = cy[s * 4 * nx], e1 = cy[s * 4 * nx + nx];
-        const double n0 = T[0] * c0 + T[1] * c1 + e0;
-        const double n1 = T[2] * c0 + T[3] * c1 + e1;
-        c0 = n0;
-        c1 = n1;
+    // ---- forward: c_{s+1} = T_s c_s + e_s --------------------------------------
+    Aff m = aff_identity();
+    if (valid) {
+        for (int s0 = sb; s0 < se; s0 += PB) {
+            double e0[PB], e1[PB];
+#pragma unroll
+            for (int u = 0; u < PB; ++u)
+                if (s0 + u < se) {
+                    e0[u] = cy[(s0 + u) * 4 * nx];
+                    e1[u] = cy[(s0 + u) * 4 * nx + nx];
+                }
+#pragma unroll
+            for (int u = 0; u < PB; ++u)
+                if (s0 + u < se) {
+                    Aff x = s0 + u == ns - 1 ? Tl : Tf;
+                    x.e0 = e0[u];
+                    x.e1 = e1[u];
+                    m = compose(x, m);
+                }
+        }
     }
-    double x0 = I.Cinv[0] * c0 + I.Cinv[1] * c1;
-    double x1 = I.Cinv[2] * c0 + I.Cinv[3] * c1;
-    c0 = x0;
-    c1 = x1;
-    for (int s = 0; s < ns; ++s) {
-        const double *T = s == ns - 1 ? I.Tl : I.Tf;
-        const double e0 = cy[s * 4 * nx], e1 = cy[s * 4 * nx + nx];
-        cy[s * 4 * nx] = c0;
-        cy[s * 4 * nx + nx] = c1;
-        const double n0 = T[0] * c0 + T[1] * c1 + e0;
-        const double n1 = T[2] * c0 + T[3] * c1 + e1;
-        c0 = n0;
-        c1 = n1;
+    xa[q][cl] = m;
+    __syncthreads();
+    Aff pre = aff_identity(), tot = aff_identity();
+#pragma unroll
+    for (int r = 0; r < kBGroups; ++r) {
+        const Aff x = xa[r][cl];
+        if (r < q) pre = compose(x, pre);
+        tot = compose(x, tot);
     }
-    // backward: top state t_s = g_s + Q_s c_s + N_s d_s, d_{s-1} = t_s (N = M)
-    double d0 = 0.0, d1 = 0.0;
-    for (int s = ns - 1; s >= 0; --s) {
-        const double *T = s == ns - 1 ? I.Tl : I.Tf;
-        const double *Q = s == ns - 1 ? I.Ql : I.Qf;
-        const double cs0 = cy[s * 4 * nx], cs1 = cy[s * 4 * nx + nx];
-        const double g0 = cy[s * 4 * nx + 2 * nx], g1 = cy[s * 4 * nx + 3 * nx];
-        const double n0 = g0 + Q[0] * cs0 + Q[1] * cs1 + T[0] * d0 + T[1] * d1;
-        const double n1 = g1 + Q[2] * cs0 + Q[3] * cs1 + T[2] * d0 + T[3] * d1;
-        d0 = n0;
-        d1 = n1;
+    __syncthreads();
+    double x0 = I.Cinv[0] * tot.e0 + I.Cinv[1] * tot.e1;
+    double x1 = I.Cinv[2] * tot.e0 + I.Cinv[3] * tot.e1;
+    double c0 = pre.a * x0 + pre.b * x1 + pre.e0;
+    double c1 = pre.c * x0 + pre.d * x1 + pre.e1;
+    if (valid) {
+        for (int s0 = sb; s0 < se; s0 += PB) {
+            double e0[PB], e1[PB];
+#pragma unroll
+            for (int u = 0; u < PB; ++u)
+                if (s0 + u < se) {
+                    e0[u] = cy[(s0 + u) * 4 * nx];
+                    e1[u] = cy[(s0 + u) * 4 * nx + nx];
+                }
+#pragma unroll
+            for (int u = 0; u < PB; ++u)
+                if (s0 + u < se) {
+                    const Aff &T = s0 + u == ns - 1 ? Tl : Tf;
+                    cy[(s0 + u) * 4 * nx] = c0;
+                    cy[(s0 + u) * 4 * nx + nx] = c1;
+                    const double n0 = T.a * c0 + T.b * c1 + e0[u];
+                    const double n1 = T.c * c0 + T.d * c1 + e1[u];
+                    c0 = n0;
+                    c1 = n1;
+                }
+        }
     }
-    x0 = I.Cinv[0] * d0 + I.Cinv[1] * d1;
-    x1 = I.Cinv[2] * d0 + I.Cinv[3] * d1;
-    d0 = x0;
-    d1 = x1;
-    for (int s = ns - 1; s >= 0; --s) {
-        const double *T = s == ns - 1 ? I.Tl : I.Tf;
-        const double *Q = s == ns - 1 ? I.Ql : I.Qf;
-        const double cs0 = cy[s * 4 * nx], cs1 = cy[s * 4 * nx + nx];
-        const double g0 = cy[s * 4 * nx + 2 * nx], g1 = cy[s * 4 * nx + 3 * nx];
-        cy[s * 4 * nx + 2 * nx] = d0;
-        cy[s * 4 * nx + 3 * nx] = d1;
-        const double n0 = g0 + Q[0] * cs0 + Q[1] * cs1 + T[0] * d0 + T[1] * d1;
-        const double n1 = g1 + Q[2] * cs0 + Q[3] * cs1 + T[2] * d0 + T[3] * d1;
-        d0 = n0;
-        d1 = n1;
+
+    // ---- backward: d_{s-1} = T_s d_s + g_s + Q_s c_s ---------------------------
+    // (every thread reads back only the c_s it wrote itself)
+    m = aff_identity();
+    if (valid) {
+        for (int s1 = se - 1; s1 >= sb; s1 -= PB) {
+            double cs0[PB], cs1[PB], g0[PB], g1[PB];
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                const int s = s1 - u;
+                if (s >= sb) {
+                    cs0[u] = cy[s * 4 * nx];
+                    cs1[u] = cy[s * 4 * nx + nx];
+                    g0[u] = cy[s * 4 * nx + 2 * nx];
+                    g1[u] = cy[s * 4 * nx + 3 * nx];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                const int s = s1 - u;
+                if (s >= sb) {
+                    const Aff &Q = s == ns - 1 ? Ql : Qf;
+                    Aff x = s == ns - 1 ? Tl : Tf;
+                    x.e0 = g0[u] + Q.a * cs0[u] + Q.b * cs1[u];
+                    x.e1 = g1[u] + Q.c * cs0[u] + Q.d * cs1[u];
+                    m = compose(x, m);
+                }
+            }
+        }
+    }
+    xa[q][cl] = m;
+    __syncthreads();
+    pre = aff_identity();
+    tot = aff_identity();
+#pragma unroll
+    for (int r = kBGroups - 1; r >= 0; --r) {
+        const Aff x = xa[r][cl];
+        if (r > q) pre = compose(x, pre);
+        tot = compose(x, tot);
+    }
+    x0 = I.Cinv[0] * tot.e0 + I.Cinv[1] * tot.e1;
+    x1 = I.Cinv[2] * tot.e0 + I.Cinv[3] * tot.e1;
+    double d0 = pre.a * x0 + pre.b * x1 + pre.e0;
+    double d1 = pre.c * x0 + pre.d * x1 + pre.e1;
+    if (valid) {
+        for (int s1 = se - 1; s1 >= sb; s1 -= PB) {
+            double cs0[PB], cs1[PB], g0[PB], g1[PB];
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                const int s = s1 - u;
+                if (s >= sb) {
+                    cs0[u] = cy[s * 4 * nx];
+                    cs1[u] = cy[s * 4 * nx + nx];
+                    g0[u] = cy[s * 4 * nx + 2 * nx];
+                    g1[u] = cy[s * 4 * nx + 3 * nx];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                const int s = s1 - u;
+                if (s >= sb) {
+                    const Aff &Q = s == ns - 1 ? Ql : Qf;
+                    const Aff &T = s == ns - 1 ? Tl : Tf;
+                    cy[s * 4 * nx + 2 * nx] = d0;
+                    cy[s * 4 * nx + 3 * nx] = d1;
+                    const double n0 = g0[u] + Q.a * cs0[u] + Q.b * cs1[u] + T.a * d0 + T.b * d1;
+                    const double n1 = g1[u] + Q.c * cs0[u] + Q.d * cs1[u] + T.c * d0 + T.d * d1;
+                    d0 = n0;
+                    d1 = n1;
+                }
+            }
+        }
     }
 }
 
@@ -380,15 +589,25 @@ __global__ void __launch_bounds__(kColsThreads) cols_phase_c(const ColsInst *__r
 }
 
 template <typename T, int BW>
-hipError_t ragged_one(const RaggedLines &a, int grid, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((ragged_lines_kernel<T, BW>), dim3(grid), dim3(64), lds, s, a);
+hipError_t ragged_one(const RaggedLines &a, int nw, int grid, size_t lds, hipStream_t s) {
+    if (nw == 4)
+        hipLaunchKernelGGL((ragged_lines_kernel<T, BW, 4>), dim3(grid), dim3(256), lds, s, a);
+    else if (nw == 2)
+        hipLaunchKernelGGL((ragged_lines_kernel<T, BW, 2>), dim3(grid), dim3(128), lds, s, a);
+    else
+        hipLaunchKernelGGL((ragged_lines_kernel<T, BW, 1>), dim3(grid), dim3(64), lds, s, a);
     return hipGetLastError();
 }
 
 template <typename T, int BW>
-hipError_t rows_one(const RowsInst *inst, int ninst, int nlines, int grid, size_t lds,
+hipError_t rows_one(const RowsInst *inst, int ninst, int nlines, int nw, int grid, size_t lds,
                     hipStream_t s) {
-    hipLaunchKernelGGL((rows_kernel<T, BW>), dim3(grid), dim3(64), lds, s, inst, ninst, nlines);
+    if (nw == 4)
+        hipLaunchKernelGGL((rows_kernel<T, BW, 4>), dim3(grid), dim3(256), lds, s, inst, ninst, nlines);
+    else if (nw == 2)
+        hipLaunchKernelGGL((rows_kernel<T, BW, 2>), dim3(grid), dim3(128), lds, s, inst, ninst, nlines);
+    else
+        hipLaunchKernelGGL((rows_kernel<T, BW, 1>), dim3(grid), dim3(64), lds, s, inst, ninst, nlines);
     return hipGetLastError();
 }
 
@@ -410,28 +629,28 @@ hipError_t cols_bw(int bw, const ColsInst *inst, int ninst, int blocksAC, int bl
 
 }  // namespace
 
-hipError_t launch_ragged_lines(int dtype, int bw, const RaggedLines &a, int grid, size_t lds,
-                               hipStream_t s) {
+hipError_t launch_ragged_lines(int dtype, int bw, const RaggedLines &a, int nw, int grid,
+                               size_t lds, hipStream_t s) {
     switch (dtype * 2 + (bw - 1)) {
-    case F64 * 2 + 0: return ragged_one<double, 1>(a, grid, lds, s);
-    case F64 * 2 + 1: return ragged_one<double, 2>(a, grid, lds, s);
-    case F32 * 2 + 0: return ragged_one<float, 1>(a, grid, lds, s);
-    case F32 * 2 + 1: return ragged_one<float, 2>(a, grid, lds, s);
-    case BF16 * 2 + 0: return ragged_one<bf16, 1>(a, grid, lds, s);
-    case BF16 * 2 + 1: return ragged_one<bf16, 2>(a, grid, lds, s);
+    case F64 * 2 + 0: return ragged_one<double, 1>(a, nw, grid, lds, s);
+    case F64 * 2 + 1: return ragged_one<double, 2>(a, nw, grid, lds, s);
+    case F32 * 2 + 0: return ragged_one<float, 1>(a, nw, grid, lds, s);
+    case F32 * 2 + 1: return ragged_one<float, 2>(a, nw, grid, lds, s);
+    case BF16 * 2 + 0: return ragged_one<bf16, 1>(a, nw, grid, lds, s);
+    case BF16 * 2 + 1: return ragged_one<bf16, 2>(a, nw, grid, lds, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_rows(int dtype, int bw, const RowsInst *inst, int ninst, int nlines, int grid,
-                       size_t lds, hipStream_t s) {
+hipError_t launch_rows(int dtype, int bw, const RowsInst *inst, int ninst, int nlines, int nw,
+                       int grid, size_t lds, hipStream_t s) {
     switch (dtype * 2 + (bw - 1)) {
-    case F64 * 2 + 0: return rows_one<double, 1>(inst, ninst, nlines, grid, lds, s);
-    case F64 * 2 + 1: return rows_one<double, 2>(inst, ninst, nlines, grid, lds, s);
-    case F32 * 2 + 0: return rows_one<float, 1>(inst, ninst, nlines, grid, lds, s);
-    case F32 * 2 + 1: return rows_one<float, 2>(inst, ninst, nlines, grid, lds, s);
-    case BF16 * 2 + 0: return rows_one<bf16, 1>(inst, ninst, nlines, grid, lds, s);
-    case BF16 * 2 + 1: return rows_one<bf16, 2>(inst, ninst, nlines, grid, lds, s);
+    case F64 * 2 + 0: return rows_one<double, 1>(inst, ninst, nlines, nw, grid, lds, s);
+    case F64 * 2 + 1: return rows_one<double, 2>(inst, ninst, nlines, nw, grid, lds, s);
+    case F32 * 2 + 0: return rows_one<float, 1>(inst, ninst, nlines, nw, grid, lds, s);
+    case F32 * 2 + 1: return rows_one<float, 2>(inst, ninst, nlines, nw, grid, lds, s);
+    case BF16 * 2 + 0: return rows_one<bf16, 1>(inst, ninst, nlines, nw, grid, lds, s);
+    case BF16 * 2 + 1: return rows_one<bf16, 2>(inst, ninst, nlines, nw, grid, lds, s);
     default: return hipErrorInvalidValue;
     }
 }

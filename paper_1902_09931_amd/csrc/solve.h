@@ -12,6 +12,8 @@
 
 #include "mxs_internal.h"
 
+#include <stdlib.h>
+
 namespace mxs {
 
 struct CyclicFactor {
@@ -22,15 +24,26 @@ struct CyclicFactor {
 // -1 for invalid input, -2 when the symbol is not positive on the circle.
 int factor_symmetric_circulant(int bw, const double *c, CyclicFactor *f);
 
-// Chunk length (even) of a line of n elements spread over the 64 lanes of a
-// wavefront; chunk l is stored in LDS at l * (k + 1).
-inline int wave_chunk(long long n) {
-    long long k = (n + 127) / 128 * 2;
+// Lines are solved by workgroups of NT = 64 * nw threads (nw = 1 or 4):
+// chunk t of k elements (k even) is stored in LDS at t * (k + 1), followed by
+// nw exchange slots of six doubles.
+inline int line_waves(long long nmax) {
+    if (const char *env = getenv("MXS_LINE_WAVES")) {
+        const int v = atoi(env);
+        if (v == 1 || v == 2 || v == 4) return v;
+    }
+    return nmax > 2048 ? 4 : 1;
+}
+inline int line_chunk(long long n, int nw) {
+    const long long nt = 64LL * nw;
+    long long k = (n + 2 * nt - 1) / (2 * nt) * 2;
     return static_cast<int>(k < 2 ? 2 : k);
 }
-inline size_t wave_line_lds_bytes(int k) { return static_cast<size_t>(64) * (k + 1) * sizeof(double); }
+inline size_t line_lds_bytes(long long nmax, int nw) {
+    return (static_cast<size_t>(64) * nw * (line_chunk(nmax, nw) + 1) + 6 * nw) * sizeof(double);
+}
 
-// --- lines solved by one wavefront each --------------------------------------
+// --- lines solved by one workgroup each --------------------------------------
 struct RaggedLines {
     const void *in;
     void *out;
@@ -52,6 +65,9 @@ struct RowsInst {
 // --- columns: three phases over segments of kSeg rows -------------------------
 constexpr int kSeg = 32;
 constexpr int kColsThreads = 256;
+// phase B: kBGroups threads per column, kBCols columns per workgroup
+constexpr int kBGroups = 8;
+constexpr int kBCols = kColsThreads / kBGroups;
 
 struct ColsInst {
     const void *rhs;            // rhs dtype
@@ -73,10 +89,10 @@ struct ColsInst {
 // Fill the column coefficients of an instance with n = ny rows.
 void fill_cols_coef(const CyclicFactor &f, int bw, int ny, ColsInst *ci);
 
-hipError_t launch_ragged_lines(int dtype, int bw, const RaggedLines &a, int grid, size_t lds,
-                               hipStream_t s);
-hipError_t launch_rows(int dtype, int bw, const RowsInst *inst, int ninst, int nlines, int grid,
-                       size_t lds, hipStream_t s);
+hipError_t launch_ragged_lines(int dtype, int bw, const RaggedLines &a, int nw, int grid,
+                               size_t lds, hipStream_t s);
+hipError_t launch_rows(int dtype, int bw, const RowsInst *inst, int ninst, int nlines, int nw,
+                       int grid, size_t lds, hipStream_t s);
 // epilogue: 0 = x = A^-1 rhs; 1 = Cahn-Hilliard update x = 2 cur - prev + A^-1 rhs.
 // (rhs dtype, output dtype) pairs: (F64,F64), (F32,F32), (BF16,BF16), (F32,BF16).
 hipError_t launch_cols(int rhs_dtype, int x_dtype, int bw, int epilogue, const ColsInst *inst,

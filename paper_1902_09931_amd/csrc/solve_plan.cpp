@@ -3,6 +3,7 @@
 #include "solve.h"
 
 #include <algorithm>
+#include <cstdio>
 #include <numeric>
 #include <vector>
 
@@ -36,7 +37,7 @@ struct SolvePlan final : mxs_plan_s {
     RowsInst rows{};
     ColsInst cols{};
     DevBuf table, carry;
-    int nlines = 0, grid = 1, blocksAC = 0, blocksB = 0;
+    int nlines = 0, grid = 1, blocksAC = 0, blocksB = 0, nw = 1;
     size_t lds = 0, bytes = 0;
     bool dirty = true;
     SolvePlan() : mxs_plan_s(KIND_SOLVE) {}
@@ -58,15 +59,15 @@ struct SolvePlan final : mxs_plan_s {
     mxs_status compute(hipStream_t s) override {
         hipError_t e = hipSuccess;
         if (geometry == MXS_LINES_RAGGED) {
-            e = launch_ragged_lines(dtype, bw, rl, grid, lds, s);
+            e = launch_ragged_lines(dtype, bw, rl, nw, grid, lds, s);
         } else if (geometry == MXS_LINES_ROWS) {
             if (dirty) {
                 e = hipMemcpyAsync(table.ptr, &rows, sizeof rows, hipMemcpyHostToDevice, s);
                 dirty = false;
             }
             if (e == hipSuccess)
-                e = launch_rows(dtype, bw, static_cast<const RowsInst *>(table.ptr), 1, nlines, grid,
-                                lds, s);
+                e = launch_rows(dtype, bw, static_cast<const RowsInst *>(table.ptr), 1, nlines, nw,
+                                grid, lds, s);
         } else {
             if (dirty) {
                 e = hipMemcpyAsync(table.ptr, &cols, sizeof cols, hipMemcpyHostToDevice, s);
@@ -83,6 +84,44 @@ struct SolvePlan final : mxs_plan_s {
         return set_io(rl.out, const_cast<void *>(r));
     }
     mxs_status rebind(const void *in, void *out) override { return set_io(in, out); }
+
+    long long nmax = 0;   // longest line (ragged, rows)
+
+    void set_waves(int w) {
+        nw = w;
+        lds = line_lds_bytes(nmax, nw);
+        grid = wave_grid(geometry == MXS_LINES_RAGGED ? rl.nlines : nlines, lds);
+    }
+
+    // Wavefronts per line: one (long chunks, few barriers) to four (more
+    // loads in flight per line); chosen by timing.
+    mxs_status autotune(hipStream_t s) override {
+        if (geometry == MXS_LINES_COLS) return MXS_OK;
+        const int start = nw;
+        int best = nw;
+        double best_t = 1e30;
+        for (int w : {1, 2, 4}) {
+            if (line_lds_bytes(nmax, w) > static_cast<size_t>(device_lds_limit())) continue;
+            set_waves(w);
+            const double t = time_launches([&] {
+                return compute(s) == MXS_OK ? hipSuccess : hipErrorLaunchFailure;
+            }, s, 1, 3);
+            if (t < 0) {
+                set_waves(start);
+                return fail(MXS_ERR_HIP, "autotune launch failed");
+            }
+            if (t < best_t) {
+                best_t = t;
+                best = w;
+            }
+        }
+        set_waves(best);
+        return MXS_OK;
+    }
+    void info(char *buf, int len) const override {
+        snprintf(buf, len, "cyclic_solve geometry=%d bw=%d dtype=%d waves_per_line=%d grid=%d lds=%zu",
+                 geometry, bw, dtype, nw, grid, lds);
+    }
 };
 
 }  // namespace
@@ -156,8 +195,8 @@ extern "C" mxs_status mxs_create_cyclic_solve(int bw, const double *coef, int ge
         p->rl.p1 = p->f.p1;
         p->rl.p2 = bw == 2 ? p->f.p2 : 0.0;
         p->rl.invK = p->f.invK;
-        p->lds = wave_line_lds_bytes(wave_chunk(nmax));
-        p->grid = wave_grid(nbatch, p->lds);
+        p->nmax = nmax;
+        p->set_waves(line_waves(nmax));
     } else {
         if (nx <= 0 || ny <= 0 || ld < nx) {
             delete p;
@@ -183,8 +222,8 @@ extern "C" mxs_status mxs_create_cyclic_solve(int bw, const double *coef, int ge
             p->rows.p2 = bw == 2 ? p->f.p2 : 0.0;
             p->rows.invK = p->f.invK;
             p->nlines = ny;
-            p->lds = wave_line_lds_bytes(wave_chunk(nx));
-            p->grid = wave_grid(ny, p->lds);
+            p->nmax = nx;
+            p->set_waves(line_waves(nx));
             e = p->table.alloc(sizeof(RowsInst));
         } else {
             fill_cols_coef(p->f, bw, ny, &p->cols);
@@ -195,7 +234,7 @@ extern "C" mxs_status mxs_create_cyclic_solve(int bw, const double *coef, int ge
             p->cols.blk0 = 0;
             p->cols.blkB0 = 0;
             p->blocksAC = p->cols.nstrips * p->cols.nseg;
-            p->blocksB = p->cols.nstrips;
+            p->blocksB = (nx + kBCols - 1) / kBCols;
             e = p->carry.alloc(sizeof(double) * 4 * static_cast<size_t>(nx) * p->cols.nseg);
             if (e == hipSuccess) e = p->table.alloc(sizeof(ColsInst));
             p->cols.carry = static_cast<double *>(p->carry.ptr);

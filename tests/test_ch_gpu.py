@@ -229,3 +229,26 @@ def test_ch_argument_errors():
     with pytest.raises(b.MxsError) as e:
         b.mxs_ch_step(0x5678, 1, False)
     assert e.value.status == b.MXS_ERR_BAD_HANDLE
+
+
+def test_autotune_keeps_the_state_and_parity():
+    """Tuning times whole steps without advancing: the step count and both
+    time levels are unchanged, and the run continues to the oracle's answer."""
+    c0 = wl.ch_initial(72, 96, seed=21)
+    g = Grid(c0)
+    try:
+        b.mxs_ch_step(g.plan, 2, True)
+        torch.cuda.synchronize()
+        before = g.state()
+        b.mxs_autotune(g.plan)
+        assert "row_waves=" in b.mxs_plan_info(g.plan)
+        assert b.mxs_ch_steps_taken(g.plan) == 2
+        after = g.state()
+        assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+        b.mxs_ch_step(g.plan, 3, True)
+        torch.cuda.synchronize()
+        _, gc = g.state()
+    finally:
+        g.close()
+    _, oc = oracle.ch_run(c0, c0, 5, g.dx, g.dy, g.dt, D, GAMMA)
+    assert rel_err(gc, oc) <= 1e-12

@@ -135,3 +135,35 @@ def test_solve_argument_errors():
     with pytest.raises(b.MxsError) as e:      # partial overlap
         b.mxs_create_cyclic_solve(1, TRI, b.MXS_LINES_RAGGED, 0, 0, 0, [0, 32], b.MXS_F64, a, a[1:])
     assert e.value.status == b.MXS_ERR_ALIAS
+
+
+@pytest.mark.parametrize("waves", ["1", "2", "4"])
+def test_every_line_workgroup_shape(monkeypatch, waves):
+    """One, two or four wavefronts per line give the same solution."""
+    monkeypatch.setenv("MXS_LINE_WAVES", waves)
+    rng = np.random.default_rng(31)
+    lengths = rng.permutation([5, 64, 65, 129, 1000, 4096, 3001, 2048, 17])
+    offs = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    r = rng.uniform(-1, 1, offs[-1])
+    drhs = to_device(r, "f64")
+    dx = torch.empty_like(drhs)
+    p = b.mxs_create_cyclic_solve(2, PENTA, b.MXS_LINES_RAGGED, 0, 0, 0, offs, b.MXS_F64, drhs, dx)
+    assert f"waves_per_line={waves}" in b.mxs_plan_info(p)
+    b.mxs_compute(p)
+    torch.cuda.synchronize()
+    b.mxs_destroy(p)
+    check(dx.double().cpu().numpy(), oracle.cyclic_solve_batch(oracle.circulant_bands(PENTA), offs, r), "f64")
+
+
+def test_autotuned_solve_keeps_parity():
+    rng = np.random.default_rng(32)
+    r = rng.uniform(-1, 1, (64, 3000))
+    drhs = to_device(r, "f64")
+    dx = torch.empty_like(drhs)
+    p = b.mxs_create_cyclic_solve(1, TRI, b.MXS_LINES_ROWS, 3000, 64, 3000, None, b.MXS_F64, drhs, dx)
+    b.mxs_autotune(p)
+    dx.zero_()
+    b.mxs_compute(p)
+    torch.cuda.synchronize()
+    b.mxs_destroy(p)
+    check(to_host(dx), oracle.cyclic_solve_grid(oracle.circulant_bands(TRI), 1, r), "f64")
