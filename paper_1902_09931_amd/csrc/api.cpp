@@ -449,7 +449,7 @@ mxs_status mxs_create_1d_batch(int nbatch, const long long *offsets, int bc, int
     p->a.offsets = static_cast<const long long *>(p->offsets.ptr);
     p->a.tile_first = static_cast<const int *>(p->tile_first.ptr);
     p->a.wts = p->wts.ptr;
-    p->grid = static_cast<int>(std::min<long long>(ntiles, 8LL * device_cu_count()));
+    p->grid = static_cast<int>(ntiles);
     register_plan(p);
     *plan = p;
     return MXS_OK;

@@ -3,10 +3,11 @@
 //
 // The concatenated array is cut into equal tiles of W = threads * V elements,
 // regardless of where signals begin and end, so every workgroup moves the
-// same number of bytes whatever the length mix.  A persistent grid walks
-// the tiles.  For each tile the workgroup stages the values (plus an x halo
-// of PAD elements each side) and the slice of signal offsets that meets the
-// tile in LDS.  Each output finds its signal by binary search in that slice.
+// same number of bytes whatever the length mix.  One workgroup per tile (the
+// launch is a single sweep over the array, like a copy): it stages the
+// values (plus an x halo of PAD elements each side) and the slice of signal
+// offsets that meets the tile in LDS, requesting all three at once.  Each
+// output finds its signal by binary search in that slice.
 // Outputs whose window stays inside their signal read LDS directly; the few
 // near a signal end wrap within the signal (periodic) and read the wrapped
 // value from LDS when it is staged, else from global memory.
@@ -44,90 +45,86 @@ __global__ void __launch_bounds__(256) stencil1d_kernel(const Stencil1DArgs a) {
     const bool periodic = a.periodic != 0;
     const int taps = a.L + a.R + 1;
 
-    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        const long long e0 = static_cast<long long>(tile) * W;
-        const int b0 = a.tile_first[tile];
-        const int cnt = a.tile_first[tile + 1] - b0 + 2;   // offsets b0 .. b_last+1
+    // one tile per workgroup: the values, their halo and the offsets of the
+    // signals meeting the tile are all requested before any is used
+    const int tile = blockIdx.x;
+    const long long e0 = static_cast<long long>(tile) * W;
+    const int b0 = a.tile_first[tile];
+    const int cnt = a.tile_first[tile + 1] - b0 + 2;   // offsets b0 .. b_last+1
+    const long long eb = e0 + static_cast<long long>(t) * V;
+    A xv[V];
+    if (a.vec_ok && eb + V <= a.total) {
+        load_vec<T>(in + eb, xv);
+    } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) xv[v] = eb + v < a.total ? to_acc<T>(in[eb + v]) : A(0);
+    }
+    A hv = A(0);
+    if (t < 2 * PAD) {
+        const long long c = t < PAD ? e0 - PAD + t : e0 + W + (t - PAD);
+        if (c >= 0 && c < a.total) hv = to_acc<T>(in[c]);
+    }
+    for (int k = t; k < cnt; k += nt) soff[k] = a.offsets[b0 + k];
+    if (a.ncoe) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) xv[v] = point_fun<A>(xv[v], coe, a.ncoe);
+        hv = point_fun<A>(hv, coe, a.ncoe);
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) lds[PAD + t * V + v] = xv[v];
+    if (t < 2 * PAD) lds[t < PAD ? t : W + t] = hv;
+    __syncthreads();
 
-        __syncthreads();   // LDS of the previous tile is no longer read
-        for (int k = t; k < cnt; k += nt) soff[k] = a.offsets[b0 + k];
-
-        const long long eb = e0 + static_cast<long long>(t) * V;
-        A xv[V];
-        if (a.vec_ok && eb + V <= a.total) {
-            load_vec<T>(in + eb, xv);
+    A res[V];
+    bool wr[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const long long e = eb + v;
+        res[v] = A(0);
+        wr[v] = false;
+        if (e >= a.total) continue;
+        int lo = 0, hi = cnt - 2;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (soff[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        const long long sb = soff[lo];
+        const long long n = soff[lo + 1] - sb;
+        const long long i = e - sb;
+        if (!periodic && (i < a.L || i > n - 1 - a.R)) continue;
+        wr[v] = true;
+        A acc = A(0);
+        if (i >= a.L && i - a.L + (NWX - 1) <= n - 1) {
+            const A *lp = lds + PAD + (e - e0) - a.L;
+#pragma unroll
+            for (int p = 0; p < NWX; ++p) acc = fma(w[p], lp[p], acc);
         } else {
-#pragma unroll
-            for (int v = 0; v < V; ++v) xv[v] = eb + v < a.total ? to_acc<T>(in[eb + v]) : A(0);
-        }
-        if (a.ncoe) {
-#pragma unroll
-            for (int v = 0; v < V; ++v) xv[v] = point_fun<A>(xv[v], coe, a.ncoe);
-        }
-#pragma unroll
-        for (int v = 0; v < V; ++v) lds[PAD + t * V + v] = xv[v];
-        for (int h = t; h < 2 * PAD; h += nt) {
-            const long long c = h < PAD ? e0 - PAD + h : e0 + W + (h - PAD);
-            A val = A(0);
-            if (c >= 0 && c < a.total) {
-                val = to_acc<T>(in[c]);
-                if (a.ncoe) val = point_fun<A>(val, coe, a.ncoe);
-            }
-            lds[h < PAD ? h : W + h] = val;
-        }
-        __syncthreads();
-
-        A res[V];
-        bool wr[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const long long e = eb + v;
-            res[v] = A(0);
-            wr[v] = false;
-            if (e >= a.total) continue;
-            int lo = 0, hi = cnt - 2;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (soff[mid] <= e) lo = mid; else hi = mid - 1;
-            }
-            const long long sb = soff[lo];
-            const long long n = soff[lo + 1] - sb;
-            const long long i = e - sb;
-            if (!periodic && (i < a.L || i > n - 1 - a.R)) continue;
-            wr[v] = true;
-            A acc = A(0);
-            if (i >= a.L && i - a.L + (NWX - 1) <= n - 1) {
-                const A *lp = lds + PAD + (e - e0) - a.L;
-#pragma unroll
-                for (int p = 0; p < NWX; ++p) acc = fma(w[p], lp[p], acc);
-            } else {
-                for (int p = 0; p < taps; ++p) {
-                    long long ii = i + p - a.L;
-                    if (ii < 0) ii += n;
-                    else if (ii >= n) ii -= n;
-                    const long long idx = sb + ii;
-                    A val;
-                    if (idx >= e0 - PAD && idx < e0 + W + PAD) {
-                        val = lds[PAD + (idx - e0)];
-                    } else {
-                        val = to_acc<T>(in[idx]);
-                        if (a.ncoe) val = point_fun<A>(val, coe, a.ncoe);
-                    }
-                    acc = fma(w[p], val, acc);
+            for (int p = 0; p < taps; ++p) {
+                long long ii = i + p - a.L;
+                if (ii < 0) ii += n;
+                else if (ii >= n) ii -= n;
+                const long long idx = sb + ii;
+                A val;
+                if (idx >= e0 - PAD && idx < e0 + W + PAD) {
+                    val = lds[PAD + (idx - e0)];
+                } else {
+                    val = to_acc<T>(in[idx]);
+                    if (a.ncoe) val = point_fun<A>(val, coe, a.ncoe);
                 }
+                acc = fma(w[p], val, acc);
             }
-            res[v] = acc;
         }
-        bool all = a.vec_ok && eb + V <= a.total;
+        res[v] = acc;
+    }
+    bool all = a.vec_ok && eb + V <= a.total;
 #pragma unroll
-        for (int v = 0; v < V; ++v) all = all && wr[v];
-        if (all) {
-            store_vec<T>(out + eb, res);
-        } else {
+    for (int v = 0; v < V; ++v) all = all && wr[v];
+    if (all) {
+        store_vec_nt<T>(out + eb, res);
+    } else {
 #pragma unroll
-            for (int v = 0; v < V; ++v)
-                if (wr[v]) out[eb + v] = from_acc<T>(res[v]);
-        }
+        for (int v = 0; v < V; ++v)
+            if (wr[v]) out[eb + v] = from_acc<T>(res[v]);
     }
 }
 
