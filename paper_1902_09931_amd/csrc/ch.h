@@ -27,8 +27,9 @@ struct RhsInst {
 
 constexpr int kRhsThreads = 256;
 
-// One launch over every instance of the table.
-hipError_t launch_ch_rhs(int state_dtype, const RhsInst *inst, int ninst, int blocks,
+// One launch over every instance of the table; map[b] is the instance of
+// workgroup b (nullptr: every workgroup belongs to instance 0).
+hipError_t launch_ch_rhs(int state_dtype, const RhsInst *inst, const int *map, int blocks,
                          hipStream_t s);
 
 // Mass: per-instance double sums of a state buffer.
@@ -38,7 +39,7 @@ struct MassInst {
     int blk0, nblk;
 };
 constexpr int kMassThreads = 256;
-hipError_t launch_ch_mass(int state_dtype, const MassInst *inst, int ninst, int blocks,
-                          double *partial, double *out, hipStream_t s);
+hipError_t launch_ch_mass(int state_dtype, const MassInst *inst, const int *map, int ninst,
+                          int blocks, double *partial, double *out, hipStream_t s);
 
 }  // namespace mxs

@@ -25,7 +25,7 @@ template <> __device__ __forceinline__ float cd_of<float>(const RhsInst &I) { re
 
 template <typename T, typename TW>
 __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__restrict__ inst,
-                                                             int ninst) {
+                                                             const int *__restrict__ map) {
     using A = typename St<T>::acc;
     constexpr int V = St<T>::V;
     constexpr int PAD = V >= 2 ? V : 2;   // two halo columns, rounded up to a vector
@@ -33,8 +33,7 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
     constexpr int XB = V + 4;             // biharmonic window per thread
     constexpr int XL = V + 2;             // Laplacian window per thread
 
-    int g = 0;
-    while (g + 1 < ninst && inst[g + 1].blk0 <= static_cast<int>(blockIdx.x)) ++g;
+    const int g = map ? map[blockIdx.x] : 0;
     const RhsInst &I = inst[g];
     const int nt = kRhsThreads;
     const int t = threadIdx.x;
@@ -232,10 +231,10 @@ __device__ double block_sum(double v, double *red) {
 
 template <typename T>
 __global__ void __launch_bounds__(kMassThreads) mass_partial_kernel(const MassInst *__restrict__ inst,
-                                                                   int ninst, double *partial) {
+                                                                   const int *__restrict__ map,
+                                                                   double *partial) {
     __shared__ double red[kMassThreads];
-    int g = 0;
-    while (g + 1 < ninst && inst[g + 1].blk0 <= static_cast<int>(blockIdx.x)) ++g;
+    const int g = map ? map[blockIdx.x] : 0;
     const MassInst &I = inst[g];
     const long long local = blockIdx.x - I.blk0;
     const long long chunk = (I.n + I.nblk - 1) / I.nblk;
@@ -259,19 +258,19 @@ __global__ void __launch_bounds__(kMassThreads) mass_final_kernel(const MassInst
 }
 
 template <typename T, typename TW>
-hipError_t rhs_one(const RhsInst *inst, int ninst, int blocks, hipStream_t s) {
+hipError_t rhs_one(const RhsInst *inst, const int *map, int blocks, hipStream_t s) {
     using A = typename St<T>::acc;
     constexpr int V = St<T>::V;
     constexpr int PAD = V >= 2 ? V : 2;
     const size_t lds = 2 * 4 * static_cast<size_t>(PAD + kRhsThreads * V + PAD) * sizeof(A);
-    hipLaunchKernelGGL((ch_rhs_kernel<T, TW>), dim3(blocks), dim3(kRhsThreads), lds, s, inst, ninst);
+    hipLaunchKernelGGL((ch_rhs_kernel<T, TW>), dim3(blocks), dim3(kRhsThreads), lds, s, inst, map);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t mass_one(const MassInst *inst, int ninst, int blocks, double *partial, double *out,
-                    hipStream_t s) {
-    hipLaunchKernelGGL((mass_partial_kernel<T>), dim3(blocks), dim3(kMassThreads), 0, s, inst, ninst,
+hipError_t mass_one(const MassInst *inst, const int *map, int ninst, int blocks, double *partial,
+                    double *out, hipStream_t s) {
+    hipLaunchKernelGGL((mass_partial_kernel<T>), dim3(blocks), dim3(kMassThreads), 0, s, inst, map,
                        partial);
     hipLaunchKernelGGL(mass_final_kernel, dim3(ninst), dim3(kMassThreads), 0, s, inst, partial, out);
     return hipGetLastError();
@@ -279,21 +278,22 @@ hipError_t mass_one(const MassInst *inst, int ninst, int blocks, double *partial
 
 }  // namespace
 
-hipError_t launch_ch_rhs(int state_dtype, const RhsInst *inst, int ninst, int blocks, hipStream_t s) {
+hipError_t launch_ch_rhs(int state_dtype, const RhsInst *inst, const int *map, int blocks,
+                         hipStream_t s) {
     switch (state_dtype) {
-    case F64: return rhs_one<double, double>(inst, ninst, blocks, s);
-    case F32: return rhs_one<float, float>(inst, ninst, blocks, s);
-    case BF16: return rhs_one<bf16, float>(inst, ninst, blocks, s);
+    case F64: return rhs_one<double, double>(inst, map, blocks, s);
+    case F32: return rhs_one<float, float>(inst, map, blocks, s);
+    case BF16: return rhs_one<bf16, float>(inst, map, blocks, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_ch_mass(int state_dtype, const MassInst *inst, int ninst, int blocks,
-                          double *partial, double *out, hipStream_t s) {
+hipError_t launch_ch_mass(int state_dtype, const MassInst *inst, const int *map, int ninst,
+                          int blocks, double *partial, double *out, hipStream_t s) {
     switch (state_dtype) {
-    case F64: return mass_one<double>(inst, ninst, blocks, partial, out, s);
-    case F32: return mass_one<float>(inst, ninst, blocks, partial, out, s);
-    case BF16: return mass_one<bf16>(inst, ninst, blocks, partial, out, s);
+    case F64: return mass_one<double>(inst, map, ninst, blocks, partial, out, s);
+    case F32: return mass_one<float>(inst, map, ninst, blocks, partial, out, s);
+    case BF16: return mass_one<bf16>(inst, map, ninst, blocks, partial, out, s);
     default: return hipErrorInvalidValue;
     }
 }

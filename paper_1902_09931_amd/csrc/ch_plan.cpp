@@ -70,6 +70,8 @@ struct CHPlan final : mxs_plan_s {
     std::vector<ColsInst> cols_h[3];
     std::vector<MassInst> mass_h[3];
     DevBuf rhs_d[3], rows_d, cols_d[3], mass_d[3];
+    // instance of every workgroup (line for the row solves); unused for one grid
+    DevBuf rhs_map, rows_map, colsAC_map, colsB_map, mass_map;
     DevBuf partial, mass_out;
     double *mass_host = nullptr;
     int rhs_blocks = 0, rhs_rows = 16, row_lines = 0, row_grid = 1, row_nw = 1, colsAC = 0, colsB = 0,
@@ -87,16 +89,28 @@ struct CHPlan final : mxs_plan_s {
     }
 
     int ninst() const { return static_cast<int>(inst.size()); }
+    const int *map_of(const DevBuf &m) const {
+        return ninst() > 1 ? static_cast<const int *>(m.ptr) : nullptr;
+    }
+
+    // Upload the instance index of every unit (workgroup or line), given the
+    // number of units of each instance.
+    static hipError_t upload_map(DevBuf &buf, const std::vector<int> &units_per_inst) {
+        std::vector<int> m;
+        for (size_t g = 0; g < units_per_inst.size(); ++g)
+            m.insert(m.end(), units_per_inst[g], static_cast<int>(g));
+        return buf.upload(m.data(), sizeof(int) * m.size());
+    }
 
     hipError_t enqueue(int r, hipStream_t s) {
-        hipError_t e = launch_ch_rhs(dtype, static_cast<const RhsInst *>(rhs_d[r].ptr), ninst(),
-                                     rhs_blocks, s);
+        hipError_t e = launch_ch_rhs(dtype, static_cast<const RhsInst *>(rhs_d[r].ptr),
+                                     map_of(rhs_map), rhs_blocks, s);
         if (e != hipSuccess) return e;
-        e = launch_rows(wdtype, 2, static_cast<const RowsInst *>(rows_d.ptr), ninst(), row_lines,
-                        row_nw, row_grid, row_lds, s);
+        e = launch_rows(wdtype, 2, static_cast<const RowsInst *>(rows_d.ptr), map_of(rows_map),
+                        row_lines, row_nw, row_grid, row_lds, s);
         if (e != hipSuccess) return e;
         return launch_cols(wdtype, dtype, 2, 1, static_cast<const ColsInst *>(cols_d[r].ptr),
-                           ninst(), colsAC, colsB, s);
+                           map_of(colsAC_map), map_of(colsB_map), colsAC, colsB, s);
     }
 
     hipError_t capture(int r) {
@@ -136,8 +150,8 @@ struct CHPlan final : mxs_plan_s {
 
     mxs_status mass(double *out, hipStream_t s) {
         const int r = static_cast<int>(steps % 3);
-        hipError_t e = launch_ch_mass(dtype, static_cast<const MassInst *>(mass_d[r].ptr), ninst(),
-                                      mass_blocks, static_cast<double *>(partial.ptr),
+        hipError_t e = launch_ch_mass(dtype, static_cast<const MassInst *>(mass_d[r].ptr),
+                                      map_of(mass_map), ninst(), mass_blocks, static_cast<double *>(partial.ptr),
                                       static_cast<double *>(mass_out.ptr), s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(mass_host, mass_out.ptr, sizeof(double) * ninst(),
@@ -208,6 +222,11 @@ struct CHPlan final : mxs_plan_s {
         hipError_t e = hipSuccess;
         for (int r = 0; r < 3 && e == hipSuccess; ++r)
             e = rhs_d[r].upload(rhs_h[r].data(), sizeof(RhsInst) * n);
+        if (e == hipSuccess && n > 1) {
+            std::vector<int> units(n);
+            for (int g = 0; g < n; ++g) units[g] = rhs_h[0][g].nstrips * rhs_h[0][g].nchunks;
+            e = upload_map(rhs_map, units);
+        }
         return e == hipSuccess ? MXS_OK : hip_fail(e, "plan tables upload");
     }
 
@@ -345,6 +364,19 @@ struct CHPlan final : mxs_plan_s {
             if (e == hipSuccess) e = mass_d[r].upload(mass_h[r].data(), sizeof(MassInst) * n);
         }
         if (e == hipSuccess) e = rows_d.upload(rows_h.data(), sizeof(RowsInst) * n);
+        if (e == hipSuccess && n > 1) {
+            std::vector<int> lines(n), ac(n), bb(n), mbk(n);
+            for (int g = 0; g < n; ++g) {
+                lines[g] = inst[g].ny;
+                ac[g] = cols_h[0][g].nstrips * cols_h[0][g].nseg;
+                bb[g] = (inst[g].nx + kBCols - 1) / kBCols;
+                mbk[g] = mass_h[0][g].nblk;
+            }
+            e = upload_map(rows_map, lines);
+            if (e == hipSuccess) e = upload_map(colsAC_map, ac);
+            if (e == hipSuccess) e = upload_map(colsB_map, bb);
+            if (e == hipSuccess) e = upload_map(mass_map, mbk);
+        }
         if (e == hipSuccess) e = partial.alloc(sizeof(double) * mass_blocks);
         if (e == hipSuccess) e = mass_out.alloc(sizeof(double) * n);
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&mass_host), sizeof(double) * n, 0);

@@ -293,11 +293,9 @@ struct RaggedSrc {
 template <typename T>
 struct RowsSrc {
     const RowsInst *inst;
-    int ninst;
+    const int *map;
     __device__ LineRef get(int li) const {
-        int g = 0;
-        while (g + 1 < ninst && inst[g + 1].line0 <= li) ++g;
-        const RowsInst &I = inst[g];
+        const RowsInst &I = inst[map ? map[li] : 0];
         const long long j = li - I.line0;
         LineRef L;
         L.in = static_cast<const T *>(I.in) + j * I.ld;
@@ -317,24 +315,20 @@ __global__ void __launch_bounds__(64 * NW) ragged_lines_kernel(const RaggedLines
 }
 
 template <typename T, int BW, int NW>
-__global__ void __launch_bounds__(64 * NW) rows_kernel(const RowsInst *__restrict__ inst, int ninst,
-                                                       int nlines) {
+__global__ void __launch_bounds__(64 * NW) rows_kernel(const RowsInst *__restrict__ inst,
+                                                       const int *__restrict__ map, int nlines) {
     extern __shared__ double smem[];
-    solve_lines<T, T, BW, NW>(RowsSrc<T>{inst, ninst}, nlines, smem);
+    solve_lines<T, T, BW, NW>(RowsSrc<T>{inst, map}, nlines, smem);
 }
 
 // ---- columns -------------------------------------------------------------------
 
-__device__ __forceinline__ int find_inst(const ColsInst *inst, int ninst, int blk, bool phaseB) {
-    int g = 0;
-    while (g + 1 < ninst && (phaseB ? inst[g + 1].blkB0 : inst[g + 1].blk0) <= blk) ++g;
-    return g;
-}
+__device__ __forceinline__ int find_inst(const int *map, int blk) { return map ? map[blk] : 0; }
 
 template <typename TR, int BW>
 __global__ void __launch_bounds__(kColsThreads) cols_phase_a(const ColsInst *__restrict__ inst,
-                                                            int ninst) {
-    const int g = find_inst(inst, ninst, blockIdx.x, false);
+                                                            const int *__restrict__ map) {
+    const int g = find_inst(map, blockIdx.x);
     const ColsInst &I = inst[g];
     const int local = blockIdx.x - I.blk0;
     const int seg = local / I.nstrips;
@@ -388,9 +382,9 @@ __device__ __forceinline__ void mat2_load(const double *m, Aff &x) {
 
 template <int BW>
 __global__ void __launch_bounds__(kColsThreads) cols_phase_b(const ColsInst *__restrict__ inst,
-                                                            int ninst) {
+                                                            const int *__restrict__ map) {
     __shared__ Aff xa[kBGroups][kBCols];
-    const int g = find_inst(inst, ninst, blockIdx.x, true);
+    const int g = find_inst(map, blockIdx.x);
     const ColsInst &I = inst[g];
     const int cl = threadIdx.x % kBCols, q = threadIdx.x / kBCols;
     const int col = (blockIdx.x - I.blkB0) * kBCols + cl;
@@ -540,8 +534,8 @@ __global__ void __launch_bounds__(kColsThreads) cols_phase_b(const ColsInst *__r
 
 template <typename TR, typename TX, int BW, int EPI>
 __global__ void __launch_bounds__(kColsThreads) cols_phase_c(const ColsInst *__restrict__ inst,
-                                                            int ninst) {
-    const int g = find_inst(inst, ninst, blockIdx.x, false);
+                                                            const int *__restrict__ map) {
+    const int g = find_inst(map, blockIdx.x);
     const ColsInst &I = inst[g];
     const int local = blockIdx.x - I.blk0;
     const int seg = local / I.nstrips;
@@ -600,31 +594,32 @@ hipError_t ragged_one(const RaggedLines &a, int nw, int grid, size_t lds, hipStr
 }
 
 template <typename T, int BW>
-hipError_t rows_one(const RowsInst *inst, int ninst, int nlines, int nw, int grid, size_t lds,
+hipError_t rows_one(const RowsInst *inst, const int *map, int nlines, int nw, int grid, size_t lds,
                     hipStream_t s) {
     if (nw == 4)
-        hipLaunchKernelGGL((rows_kernel<T, BW, 4>), dim3(grid), dim3(256), lds, s, inst, ninst, nlines);
+        hipLaunchKernelGGL((rows_kernel<T, BW, 4>), dim3(grid), dim3(256), lds, s, inst, map, nlines);
     else if (nw == 2)
-        hipLaunchKernelGGL((rows_kernel<T, BW, 2>), dim3(grid), dim3(128), lds, s, inst, ninst, nlines);
+        hipLaunchKernelGGL((rows_kernel<T, BW, 2>), dim3(grid), dim3(128), lds, s, inst, map, nlines);
     else
-        hipLaunchKernelGGL((rows_kernel<T, BW, 1>), dim3(grid), dim3(64), lds, s, inst, ninst, nlines);
+        hipLaunchKernelGGL((rows_kernel<T, BW, 1>), dim3(grid), dim3(64), lds, s, inst, map, nlines);
     return hipGetLastError();
 }
 
 template <typename TR, typename TX, int BW, int EPI>
-hipError_t cols_one(const ColsInst *inst, int ninst, int blocksAC, int blocksB, hipStream_t s) {
-    hipLaunchKernelGGL((cols_phase_a<TR, BW>), dim3(blocksAC), dim3(kColsThreads), 0, s, inst, ninst);
-    hipLaunchKernelGGL((cols_phase_b<BW>), dim3(blocksB), dim3(kColsThreads), 0, s, inst, ninst);
+hipError_t cols_one(const ColsInst *inst, const int *mapAC, const int *mapB, int blocksAC,
+                    int blocksB, hipStream_t s) {
+    hipLaunchKernelGGL((cols_phase_a<TR, BW>), dim3(blocksAC), dim3(kColsThreads), 0, s, inst, mapAC);
+    hipLaunchKernelGGL((cols_phase_b<BW>), dim3(blocksB), dim3(kColsThreads), 0, s, inst, mapB);
     hipLaunchKernelGGL((cols_phase_c<TR, TX, BW, EPI>), dim3(blocksAC), dim3(kColsThreads), 0, s,
-                       inst, ninst);
+                       inst, mapAC);
     return hipGetLastError();
 }
 
 template <typename TR, typename TX, int EPI>
-hipError_t cols_bw(int bw, const ColsInst *inst, int ninst, int blocksAC, int blocksB,
-                   hipStream_t s) {
-    return bw == 1 ? cols_one<TR, TX, 1, EPI>(inst, ninst, blocksAC, blocksB, s)
-                   : cols_one<TR, TX, 2, EPI>(inst, ninst, blocksAC, blocksB, s);
+hipError_t cols_bw(int bw, const ColsInst *inst, const int *mapAC, const int *mapB, int blocksAC,
+                   int blocksB, hipStream_t s) {
+    return bw == 1 ? cols_one<TR, TX, 1, EPI>(inst, mapAC, mapB, blocksAC, blocksB, s)
+                   : cols_one<TR, TX, 2, EPI>(inst, mapAC, mapB, blocksAC, blocksB, s);
 }
 
 }  // namespace
@@ -642,30 +637,30 @@ hipError_t launch_ragged_lines(int dtype, int bw, const RaggedLines &a, int nw, 
     }
 }
 
-hipError_t launch_rows(int dtype, int bw, const RowsInst *inst, int ninst, int nlines, int nw,
+hipError_t launch_rows(int dtype, int bw, const RowsInst *inst, const int *map, int nlines, int nw,
                        int grid, size_t lds, hipStream_t s) {
     switch (dtype * 2 + (bw - 1)) {
-    case F64 * 2 + 0: return rows_one<double, 1>(inst, ninst, nlines, nw, grid, lds, s);
-    case F64 * 2 + 1: return rows_one<double, 2>(inst, ninst, nlines, nw, grid, lds, s);
-    case F32 * 2 + 0: return rows_one<float, 1>(inst, ninst, nlines, nw, grid, lds, s);
-    case F32 * 2 + 1: return rows_one<float, 2>(inst, ninst, nlines, nw, grid, lds, s);
-    case BF16 * 2 + 0: return rows_one<bf16, 1>(inst, ninst, nlines, nw, grid, lds, s);
-    case BF16 * 2 + 1: return rows_one<bf16, 2>(inst, ninst, nlines, nw, grid, lds, s);
+    case F64 * 2 + 0: return rows_one<double, 1>(inst, map, nlines, nw, grid, lds, s);
+    case F64 * 2 + 1: return rows_one<double, 2>(inst, map, nlines, nw, grid, lds, s);
+    case F32 * 2 + 0: return rows_one<float, 1>(inst, map, nlines, nw, grid, lds, s);
+    case F32 * 2 + 1: return rows_one<float, 2>(inst, map, nlines, nw, grid, lds, s);
+    case BF16 * 2 + 0: return rows_one<bf16, 1>(inst, map, nlines, nw, grid, lds, s);
+    case BF16 * 2 + 1: return rows_one<bf16, 2>(inst, map, nlines, nw, grid, lds, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_cols(int rhs_dtype, int x_dtype, int bw, int epilogue, const ColsInst *inst,
-                       int ninst, int blocksAC, int blocksB, hipStream_t s) {
+                       const int *mapAC, const int *mapB, int blocksAC, int blocksB, hipStream_t s) {
     if (bw != 1 && bw != 2) return hipErrorInvalidValue;
     if (epilogue == 0) {
-        if (rhs_dtype == F64 && x_dtype == F64) return cols_bw<double, double, 0>(bw, inst, ninst, blocksAC, blocksB, s);
-        if (rhs_dtype == F32 && x_dtype == F32) return cols_bw<float, float, 0>(bw, inst, ninst, blocksAC, blocksB, s);
-        if (rhs_dtype == BF16 && x_dtype == BF16) return cols_bw<bf16, bf16, 0>(bw, inst, ninst, blocksAC, blocksB, s);
+        if (rhs_dtype == F64 && x_dtype == F64) return cols_bw<double, double, 0>(bw, inst, mapAC, mapB, blocksAC, blocksB, s);
+        if (rhs_dtype == F32 && x_dtype == F32) return cols_bw<float, float, 0>(bw, inst, mapAC, mapB, blocksAC, blocksB, s);
+        if (rhs_dtype == BF16 && x_dtype == BF16) return cols_bw<bf16, bf16, 0>(bw, inst, mapAC, mapB, blocksAC, blocksB, s);
     } else if (bw == 2) {
-        if (rhs_dtype == F64 && x_dtype == F64) return cols_one<double, double, 2, 1>(inst, ninst, blocksAC, blocksB, s);
-        if (rhs_dtype == F32 && x_dtype == F32) return cols_one<float, float, 2, 1>(inst, ninst, blocksAC, blocksB, s);
-        if (rhs_dtype == F32 && x_dtype == BF16) return cols_one<float, bf16, 2, 1>(inst, ninst, blocksAC, blocksB, s);
+        if (rhs_dtype == F64 && x_dtype == F64) return cols_one<double, double, 2, 1>(inst, mapAC, mapB, blocksAC, blocksB, s);
+        if (rhs_dtype == F32 && x_dtype == F32) return cols_one<float, float, 2, 1>(inst, mapAC, mapB, blocksAC, blocksB, s);
+        if (rhs_dtype == F32 && x_dtype == BF16) return cols_one<float, bf16, 2, 1>(inst, mapAC, mapB, blocksAC, blocksB, s);
     }
     return hipErrorInvalidValue;
 }

@@ -91,11 +91,13 @@ void fill_cols_coef(const CyclicFactor &f, int bw, int ny, ColsInst *ci);
 
 hipError_t launch_ragged_lines(int dtype, int bw, const RaggedLines &a, int nw, int grid,
                                size_t lds, hipStream_t s);
-hipError_t launch_rows(int dtype, int bw, const RowsInst *inst, int ninst, int nlines, int nw,
+// map[li] (map[b]) is the instance of line li (workgroup b); nullptr: all
+// belong to instance 0.
+hipError_t launch_rows(int dtype, int bw, const RowsInst *inst, const int *map, int nlines, int nw,
                        int grid, size_t lds, hipStream_t s);
 // epilogue: 0 = x = A^-1 rhs; 1 = Cahn-Hilliard update x = 2 cur - prev + A^-1 rhs.
 // (rhs dtype, output dtype) pairs: (F64,F64), (F32,F32), (BF16,BF16), (F32,BF16).
 hipError_t launch_cols(int rhs_dtype, int x_dtype, int bw, int epilogue, const ColsInst *inst,
-                       int ninst, int blocksAC, int blocksB, hipStream_t s);
+                       const int *mapAC, const int *mapB, int blocksAC, int blocksB, hipStream_t s);
 
 }  // namespace mxs

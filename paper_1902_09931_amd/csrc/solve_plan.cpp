@@ -66,16 +66,16 @@ struct SolvePlan final : mxs_plan_s {
                 dirty = false;
             }
             if (e == hipSuccess)
-                e = launch_rows(dtype, bw, static_cast<const RowsInst *>(table.ptr), 1, nlines, nw,
-                                grid, lds, s);
+                e = launch_rows(dtype, bw, static_cast<const RowsInst *>(table.ptr), nullptr, nlines,
+                                nw, grid, lds, s);
         } else {
             if (dirty) {
                 e = hipMemcpyAsync(table.ptr, &cols, sizeof cols, hipMemcpyHostToDevice, s);
                 dirty = false;
             }
             if (e == hipSuccess)
-                e = launch_cols(dtype, dtype, bw, 0, static_cast<const ColsInst *>(table.ptr), 1,
-                                blocksAC, blocksB, s);
+                e = launch_cols(dtype, dtype, bw, 0, static_cast<const ColsInst *>(table.ptr), nullptr,
+                                nullptr, blocksAC, blocksB, s);
         }
         return e == hipSuccess ? MXS_OK : hip_fail(e, "cyclic solve launch");
     }
