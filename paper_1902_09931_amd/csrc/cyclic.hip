@@ -226,14 +226,14 @@ __device__ void solve_lines(const Src &src, int nlines, double *smem) {
     constexpr int NT = 64 * NW;
     constexpr int U = 32;
     const int t = threadIdx.x;
-    double r[U];
+    // raw storage values: every load is unconditional (index clamped into
+    // the line) so all U are in flight at once; conversion waits for the
+    // copy into LDS
+    TI r[U];
     auto fetch = [&](const LineRef &L, int b0) {
         const TI *in = static_cast<const TI *>(L.in);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = b0 + u * NT + t;
-            r[u] = i < L.n ? to_f64<TI>(in[i]) : 0.0;
-        }
+        for (int u = 0; u < U; ++u) r[u] = in[min(b0 + u * NT + t, L.n - 1)];
     };
     int li = blockIdx.x;
     LineRef L{};
@@ -253,7 +253,7 @@ __device__ void solve_lines(const Src &src, int nlines, double *smem) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int i = b0 + u * NT + t;
-                if (i < n) line[lds_pos(i, k, kinv)] = r[u];
+                if (i < n) line[lds_pos(i, k, kinv)] = to_f64<TI>(r[u]);
             }
         }
         __syncthreads();
@@ -325,6 +325,41 @@ __global__ void __launch_bounds__(64 * NW) rows_kernel(const RowsInst *__restric
 
 __device__ __forceinline__ int find_inst(const int *map, int blk) { return map ? map[blk] : 0; }
 
+// Forward recurrence from zero over one segment, then the backward one from
+// zero over its output; returns both end states.  FULL: the segment has
+// kSeg rows, so the body has no branch and every load can be in flight at
+// once.
+template <typename TR, int BW, bool FULL>
+__device__ __forceinline__ void seg_a(const TR *rhs, long long ld, int len, double p1, double p2,
+                                      double &s0, double &s1, double &t0, double &t1) {
+    const int n = FULL ? kSeg : len;
+    TR raw[kSeg];
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j)
+        if (j < n) raw[j] = rhs[static_cast<long long>(j) * ld];
+    double y[kSeg];
+    s0 = s1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j) {
+        if (j < n) {
+            const double b = to_f64<TR>(raw[j]);
+            const double v = BW == 2 ? fma(p2, s1, fma(p1, s0, b)) : fma(p1, s0, b);
+            y[j] = v;
+            s1 = s0;
+            s0 = v;
+        }
+    }
+    t0 = t1 = 0.0;
+#pragma unroll
+    for (int j = kSeg - 1; j >= 0; --j) {
+        if (j < n) {
+            const double v = BW == 2 ? fma(p2, t1, fma(p1, t0, y[j])) : fma(p1, t0, y[j]);
+            t1 = t0;
+            t0 = v;
+        }
+    }
+}
+
 template <typename TR, int BW>
 __global__ void __launch_bounds__(kColsThreads) cols_phase_a(const ColsInst *__restrict__ inst,
                                                             const int *__restrict__ map) {
@@ -338,29 +373,11 @@ __global__ void __launch_bounds__(kColsThreads) cols_phase_a(const ColsInst *__r
     const int r0 = seg * kSeg;
     const int len = min(kSeg, I.ny - r0);
     const TR *rhs = static_cast<const TR *>(I.rhs) + static_cast<long long>(r0) * I.ld + i;
-    const double p1 = I.p1, p2 = I.p2;
-
-    double y[kSeg];
-    double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-    for (int j = 0; j < kSeg; ++j) {
-        if (j < len) {
-            const double b = to_f64<TR>(rhs[static_cast<long long>(j) * I.ld]);
-            const double v = BW == 2 ? fma(p2, s1, fma(p1, s0, b)) : fma(p1, s0, b);
-            y[j] = v;
-            s1 = s0;
-            s0 = v;
-        }
-    }
-    double t0 = 0.0, t1 = 0.0;
-#pragma unroll
-    for (int j = kSeg - 1; j >= 0; --j) {
-        if (j < len) {
-            const double v = BW == 2 ? fma(p2, t1, fma(p1, t0, y[j])) : fma(p1, t0, y[j]);
-            t1 = t0;
-            t0 = v;
-        }
-    }
+    double s0, s1, t0, t1;
+    if (len == kSeg)
+        seg_a<TR, BW, true>(rhs, I.ld, len, I.p1, I.p2, s0, s1, t0, t1);
+    else
+        seg_a<TR, BW, false>(rhs, I.ld, len, I.p1, I.p2, s0, s1, t0, t1);
     double *cy = I.carry + static_cast<long long>(seg) * 4 * I.nx + i;
     cy[0] = s0;
     cy[I.nx] = s1;
@@ -532,6 +549,57 @@ __global__ void __launch_bounds__(kColsThreads) cols_phase_b(const ColsInst *__r
     }
 }
 
+// Both recurrences over one segment from its true incoming states, then the
+// output (EPI 1: the Cahn-Hilliard update x = 2 cur - prev + v / K).  FULL as
+// in seg_a.
+template <typename TR, typename TX, int BW, int EPI, bool FULL>
+__device__ __forceinline__ void seg_c(const TR *rhs, TX *x, const TX *cur, const TX *prev,
+                                      long long ld, int len, double p1, double p2, double invK,
+                                      double s0, double s1, double t0, double t1) {
+    const int n = FULL ? kSeg : len;
+    TR raw[kSeg];
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j)
+        if (j < n) raw[j] = rhs[static_cast<long long>(j) * ld];
+    double y[kSeg];
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j) {
+        if (j < n) {
+            const double b = to_f64<TR>(raw[j]);
+            const double v = BW == 2 ? fma(p2, s1, fma(p1, s0, b)) : fma(p1, s0, b);
+            y[j] = v;
+            s1 = s0;
+            s0 = v;
+        }
+    }
+    // backward pass in groups of G rows; the group's cur/prev values are
+    // requested together before any of its outputs is stored
+    constexpr int G = 8;
+    static_assert(kSeg % G == 0, "segment must be a whole number of groups");
+#pragma unroll
+    for (int jg = kSeg - G; jg >= 0; jg -= G) {
+        double cb[G];
+        if (EPI == 1) {
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                const long long o = static_cast<long long>(jg + q) * ld;
+                if (jg + q < n) cb[q] = 2.0 * to_f64<TX>(cur[o]) - to_f64<TX>(prev[o]);
+            }
+        }
+#pragma unroll
+        for (int q = G - 1; q >= 0; --q) {
+            const int j = jg + q;
+            if (j < n) {
+                const double v = BW == 2 ? fma(p2, t1, fma(p1, t0, y[j])) : fma(p1, t0, y[j]);
+                t1 = t0;
+                t0 = v;
+                const long long o = static_cast<long long>(j) * ld;
+                x[o] = from_f64<TX>(EPI == 1 ? cb[q] + v * invK : v * invK);
+            }
+        }
+    }
+}
+
 template <typename TR, typename TX, int BW, int EPI>
 __global__ void __launch_bounds__(kColsThreads) cols_phase_c(const ColsInst *__restrict__ inst,
                                                             const int *__restrict__ map) {
@@ -546,40 +614,16 @@ __global__ void __launch_bounds__(kColsThreads) cols_phase_c(const ColsInst *__r
     const int len = min(kSeg, I.ny - r0);
     const long long off = static_cast<long long>(r0) * I.ld + i;
     const TR *rhs = static_cast<const TR *>(I.rhs) + off;
-    const double p1 = I.p1, p2 = I.p2;
     const double *cy = I.carry + static_cast<long long>(seg) * 4 * I.nx + i;
-    double s0 = cy[0], s1 = cy[I.nx];
-    double t0 = cy[2 * I.nx], t1 = cy[3 * I.nx];
-
-    double y[kSeg];
-#pragma unroll
-    for (int j = 0; j < kSeg; ++j) {
-        if (j < len) {
-            const double b = to_f64<TR>(rhs[static_cast<long long>(j) * I.ld]);
-            const double v = BW == 2 ? fma(p2, s1, fma(p1, s0, b)) : fma(p1, s0, b);
-            y[j] = v;
-            s1 = s0;
-            s0 = v;
-        }
-    }
+    const double s0 = cy[0], s1 = cy[I.nx];
+    const double t0 = cy[2 * I.nx], t1 = cy[3 * I.nx];
     TX *x = static_cast<TX *>(I.x) + off;
     const TX *cur = static_cast<const TX *>(I.cur) + off;
     const TX *prev = static_cast<const TX *>(I.prev) + off;
-#pragma unroll
-    for (int j = kSeg - 1; j >= 0; --j) {
-        if (j < len) {
-            const double v = BW == 2 ? fma(p2, t1, fma(p1, t0, y[j])) : fma(p1, t0, y[j]);
-            t1 = t0;
-            t0 = v;
-            const long long o = static_cast<long long>(j) * I.ld;
-            if (EPI == 1) {
-                const double cb = 2.0 * to_f64<TX>(cur[o]) - to_f64<TX>(prev[o]);
-                x[o] = from_f64<TX>(cb + v * I.invK);
-            } else {
-                x[o] = from_f64<TX>(v * I.invK);
-            }
-        }
-    }
+    if (len == kSeg)
+        seg_c<TR, TX, BW, EPI, true>(rhs, x, cur, prev, I.ld, len, I.p1, I.p2, I.invK, s0, s1, t0, t1);
+    else
+        seg_c<TR, TX, BW, EPI, false>(rhs, x, cur, prev, I.ld, len, I.p1, I.p2, I.invK, s0, s1, t0, t1);
 }
 
 template <typename T, int BW>
