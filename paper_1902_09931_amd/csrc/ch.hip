@@ -54,9 +54,9 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
     const int ib = i0 + t * V;
     const int nx = I.nx, ny = I.ny;
     const bool full_vec = ((nx % V) == 0) && (ib + V <= nx);
-    const T *cur = static_cast<const T *>(I.cur);
-    const T *prev = static_cast<const T *>(I.prev);
-    TW *R = static_cast<TW *>(I.R);
+    const gptr<const T> cur = as_global(static_cast<const T *>(I.cur));
+    const gptr<const T> prev = as_global(static_cast<const T *>(I.prev));
+    const gptr<TW> R = as_global(static_cast<TW *>(I.R));
     const A cdiff = cd_of<A>(I);
 
     A acc[5][V];
@@ -74,8 +74,8 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int r = static_cast<int>(wrap_ll(j0 - 2 + s0 + u, ny));
-            const T *cr = cur + static_cast<long long>(r) * nx;
-            const T *pr = prev + static_cast<long long>(r) * nx;
+            const gptr<const T> cr = cur + static_cast<long long>(r) * nx;
+            const gptr<const T> pr = prev + static_cast<long long>(r) * nx;
             if (full_vec) {
                 load_vec<T>(cr + ib, c[u]);
                 load_vec<T>(pr + ib, p[u]);
@@ -83,8 +83,8 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     const int col = static_cast<int>(wrap_ll(ib + v, nx));
-                    c[u][v] = to_acc<T>(cr[col]);
-                    p[u][v] = to_acc<T>(pr[col]);
+                    c[u][v] = to_acc<T>(gld<T>(cr, col));
+                    p[u][v] = to_acc<T>(gld<T>(pr, col));
                 }
             }
         }
@@ -99,8 +99,8 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
                 const long long col = hh < PAD ? static_cast<long long>(i0) - PAD + hh
                                                : static_cast<long long>(i0) + W + (hh - PAD);
                 const long long o = static_cast<long long>(r) * nx + wrap_ll(col, nx);
-                vc = to_acc<T>(cur[o]);
-                vp = to_acc<T>(prev[o]);
+                vc = to_acc<T>(gld<T>(cur, o));
+                vp = to_acc<T>(gld<T>(prev, o));
             }
             hc[q] = vc;
             hp[q] = vp;
@@ -175,13 +175,13 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
 
                 const int jj = s - 4;
                 if (jj >= 0 && jj < H) {
-                    TW *rowp = R + static_cast<long long>(j0 + jj) * nx;
+                    const gptr<TW> rowp = R + static_cast<long long>(j0 + jj) * nx;
                     if (full_vec) {
                         store_vec_nt<TW>(rowp + ib, acc[0]);
                     } else {
 #pragma unroll
                         for (int v = 0; v < V; ++v)
-                            if (ib + v < nx) rowp[ib + v] = from_acc<TW>(acc[0][v]);
+                            if (ib + v < nx) gst<TW>(rowp, ib + v, from_acc<TW>(acc[0][v]));
                     }
                 }
 #pragma unroll
@@ -209,10 +209,10 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
 
 // ---- mass ------------------------------------------------------------------------
 
-template <typename T> __device__ __forceinline__ double elem_f64(const T *p, long long i);
-template <> __device__ __forceinline__ double elem_f64<double>(const double *p, long long i) { return p[i]; }
-template <> __device__ __forceinline__ double elem_f64<float>(const float *p, long long i) { return p[i]; }
-template <> __device__ __forceinline__ double elem_f64<bf16>(const bf16 *p, long long i) {
+template <typename T> __device__ __forceinline__ double elem_f64(gptr<const T> p, long long i);
+template <> __device__ __forceinline__ double elem_f64<double>(gptr<const double> p, long long i) { return p[i]; }
+template <> __device__ __forceinline__ double elem_f64<float>(gptr<const float> p, long long i) { return p[i]; }
+template <> __device__ __forceinline__ double elem_f64<bf16>(gptr<const bf16> p, long long i) {
     return bf16_to_float(p[i].bits);
 }
 
@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(kMassThreads) mass_partial_kernel(const MassIn
     const long long chunk = (I.n + I.nblk - 1) / I.nblk;
     const long long a = local * chunk;
     const long long b = min(I.n, a + chunk);
-    const T *c = static_cast<const T *>(I.c);
+    const gptr<const T> c = as_global(static_cast<const T *>(I.c));
     double s = 0.0;
     for (long long i = a + threadIdx.x; i < b; i += kMassThreads) s += elem_f64<T>(c, i);
     const double tot = block_sum(s, red);

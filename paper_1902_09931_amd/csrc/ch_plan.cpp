@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <numeric>
 #include <vector>
 
 namespace mxs {
@@ -72,6 +73,14 @@ struct CHPlan final : mxs_plan_s {
     DevBuf rhs_d[3], rows_d, cols_d[3], mass_d[3];
     // instance of every workgroup (line for the row solves); unused for one grid
     DevBuf rhs_map, rows_map, colsAC_map, colsB_map, mass_map;
+    // power tables of the row operators (register row kernel), one per instance
+    DevBuf pows;
+    // register row kernel: lines numbered by register class, one launch per
+    // class; empty when the LDS kernel solves the rows
+    struct RowRange {
+        int nb, first, count;
+    };
+    std::vector<RowRange> row_ranges;
     DevBuf partial, mass_out;
     double *mass_host = nullptr;
     int rhs_blocks = 0, rhs_rows = 16, row_lines = 0, row_grid = 1, row_nw = 1, colsAC = 0, colsB = 0,
@@ -106,8 +115,12 @@ struct CHPlan final : mxs_plan_s {
         hipError_t e = launch_ch_rhs(dtype, static_cast<const RhsInst *>(rhs_d[r].ptr),
                                      map_of(rhs_map), rhs_blocks, s);
         if (e != hipSuccess) return e;
-        e = launch_rows(wdtype, 2, static_cast<const RowsInst *>(rows_d.ptr), map_of(rows_map),
-                        row_lines, row_nw, row_grid, row_lds, s);
+        const RowsInst *ri = static_cast<const RowsInst *>(rows_d.ptr);
+        if (row_ranges.empty())
+            e = launch_rows(wdtype, 2, ri, map_of(rows_map), row_lines, row_nw, row_grid, row_lds, s);
+        for (size_t q = 0; q < row_ranges.size() && e == hipSuccess; ++q)
+            e = launch_wave_rows(wdtype, 2, row_ranges[q].nb, ri, map_of(rows_map), row_ranges[q].first,
+                                 row_ranges[q].count, s);
         if (e != hipSuccess) return e;
         return launch_cols(wdtype, dtype, 2, 1, static_cast<const ColsInst *>(cols_d[r].ptr),
                            map_of(colsAC_map), map_of(colsB_map), colsAC, colsB, s);
@@ -257,6 +270,7 @@ struct CHPlan final : mxs_plan_s {
             if (st) return st;
             for (int w : {1, 2, 4}) {
                 if (line_lds_bytes(max_nx, w) > static_cast<size_t>(device_lds_limit())) continue;
+                if (!row_ranges.empty() && w != row_nw) continue;   // no LDS kernel to shape
                 set_row_waves(w);
                 const double t = time_launches([&] { return enqueue(r, s); }, s, 1, 3);
                 if (t < 0) return hip_fail(hipGetLastError(), "autotune launch");
@@ -273,8 +287,13 @@ struct CHPlan final : mxs_plan_s {
     }
 
     void info(char *buf, int len) const override {
-        snprintf(buf, len, "ch instances=%d dtype=%d rhs_rows=%d rhs_blocks=%d row_waves=%d row_grid=%d cols_blocks=%d",
-                 ninst(), dtype, rhs_rows, rhs_blocks, row_nw, row_grid, colsAC);
+        int n = snprintf(buf, len, "ch instances=%d dtype=%d rhs_rows=%d rhs_blocks=%d cols_blocks=%d",
+                         ninst(), dtype, rhs_rows, rhs_blocks, colsAC);
+        if (row_ranges.empty() && n < len)
+            n += snprintf(buf + n, len - n, " row_kernel=lds row_waves=%d row_grid=%d", row_nw, row_grid);
+        for (size_t q = 0; q < row_ranges.size() && n < len; ++q)
+            n += snprintf(buf + n, len - n, " row_kernel=register(nb=%d lines=%d)", row_ranges[q].nb,
+                          row_ranges[q].count);
     }
 
     mxs_status build() {
@@ -287,7 +306,9 @@ struct CHPlan final : mxs_plan_s {
         // row solves (in place on w) and column solves (w -> C^{n+1})
         rows_h.resize(n);
         for (int r = 0; r < 3; ++r) cols_h[r].resize(n);
-        int line = 0, bAC = 0, bB = 0;
+        const bool reg_rows = maxnx <= kWaveLineMax && !force_lds_lines();
+        std::vector<double> pt(static_cast<size_t>(4) * kPowEntries * n);
+        int bAC = 0, bB = 0;
         for (int g = 0; g < n; ++g) {
             Inst &I = inst[g];
             const double a = 2.0 / 3.0 * D * gamma * I.dt;
@@ -303,12 +324,11 @@ struct CHPlan final : mxs_plan_s {
             ro.ld = I.nx;
             ro.nx = I.nx;
             ro.ny = I.ny;
-            ro.line0 = line;
             ro.p1 = fx.p1;
             ro.p2 = fx.p2;
             ro.invK = fx.invK;
             rows_h[g] = ro;
-            line += I.ny;
+            fill_pow_table(fx, 2, pt.data() + static_cast<size_t>(4) * kPowEntries * g);
 
             ColsInst co{};
             fill_cols_coef(fy, 2, I.ny, &co);
@@ -331,6 +351,29 @@ struct CHPlan final : mxs_plan_s {
                 cc.x = I.buf[(r + 2) % 3];
                 cols_h[r][g] = cc;
             }
+        }
+        // global line numbers: instances grouped by register class, so that
+        // every class is one contiguous range of lines
+        {
+            hipError_t pe = pows.upload(pt.data(), sizeof(double) * pt.size());
+            if (pe != hipSuccess) return hip_fail(pe, "power table upload");
+        }
+        std::vector<int> by_class(n);
+        std::iota(by_class.begin(), by_class.end(), 0);
+        if (reg_rows)
+            std::stable_sort(by_class.begin(), by_class.end(),
+                             [&](int a, int b) { return wave_nb(inst[a].nx) < wave_nb(inst[b].nx); });
+        row_ranges.clear();
+        int line = 0;
+        for (int g : by_class) {
+            rows_h[g].line0 = line;
+            rows_h[g].pow = static_cast<const double *>(pows.ptr) + static_cast<size_t>(4) * kPowEntries * g;
+            if (reg_rows) {
+                const int nb = wave_nb(inst[g].nx);
+                if (row_ranges.empty() || row_ranges.back().nb != nb) row_ranges.push_back({nb, line, 0});
+                row_ranges.back().count += inst[g].ny;
+            }
+            line += inst[g].ny;
         }
         row_lines = line;
         colsAC = bAC;
@@ -365,14 +408,16 @@ struct CHPlan final : mxs_plan_s {
         }
         if (e == hipSuccess) e = rows_d.upload(rows_h.data(), sizeof(RowsInst) * n);
         if (e == hipSuccess && n > 1) {
-            std::vector<int> lines(n), ac(n), bb(n), mbk(n);
+            std::vector<int> ac(n), bb(n), mbk(n);
             for (int g = 0; g < n; ++g) {
-                lines[g] = inst[g].ny;
                 ac[g] = cols_h[0][g].nstrips * cols_h[0][g].nseg;
                 bb[g] = (inst[g].nx + kBCols - 1) / kBCols;
                 mbk[g] = mass_h[0][g].nblk;
             }
-            e = upload_map(rows_map, lines);
+            std::vector<int> line_inst(row_lines);
+            for (int g = 0; g < n; ++g)
+                std::fill(line_inst.begin() + rows_h[g].line0, line_inst.begin() + rows_h[g].line0 + inst[g].ny, g);
+            e = rows_map.upload(line_inst.data(), sizeof(int) * line_inst.size());
             if (e == hipSuccess) e = upload_map(colsAC_map, ac);
             if (e == hipSuccess) e = upload_map(colsB_map, bb);
             if (e == hipSuccess) e = upload_map(mass_map, mbk);

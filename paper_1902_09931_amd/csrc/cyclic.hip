@@ -23,36 +23,11 @@
 //      forward incoming state c_s and backward incoming state d_s;
 //   C. per segment: both recurrences again from (c_s, d_s), then the output
 //      (optionally fused with the Cahn-Hilliard update C^{n+1} = Cbar + v).
-#include "solve.h"
+#include "lines_dev.h"
 
 namespace mxs {
 
 namespace {
-
-template <typename T> __device__ __forceinline__ double to_f64(T v);
-template <> __device__ __forceinline__ double to_f64<double>(double v) { return v; }
-template <> __device__ __forceinline__ double to_f64<float>(float v) { return static_cast<double>(v); }
-template <> __device__ __forceinline__ double to_f64<bf16>(bf16 v) {
-    return static_cast<double>(bf16_to_float(v.bits));
-}
-template <typename T> __device__ __forceinline__ T from_f64(double v);
-template <> __device__ __forceinline__ double from_f64<double>(double v) { return v; }
-template <> __device__ __forceinline__ float from_f64<float>(double v) { return static_cast<float>(v); }
-// double -> bf16 rounds once, to nearest even, via the exact float split:
-// the float nearest to v can round the wrong way only at a bf16 tie; the
-// remainder v - float(v) decides that case.
-template <> __device__ __forceinline__ bf16 from_f64<bf16>(double v) {
-    const float f = static_cast<float>(v);
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return bf16{float_to_bf16(f)};
-    const double rem = v - static_cast<double>(f);
-    if ((u & 0xffffu) == 0x8000u && rem != 0.0) {
-        // exactly halfway in float but not in double: round by the remainder
-        const bool up = (rem > 0) == ((u & 0x80000000u) == 0);
-        return bf16{static_cast<uint16_t>((u >> 16) + (up ? 1u : 0u))};
-    }
-    return bf16{float_to_bf16(f)};
-}
 
 // ---- affine maps on the 2-vector state (y_i, y_{i-1}) ----------------------
 struct Aff {
@@ -147,7 +122,7 @@ __device__ __forceinline__ int lds_pos(int i, int k, float kinv) {
 // threads of the workgroup (REV: the index order reversed, i.e. the backward
 // recurrence).  xchg holds NW affine maps in LDS.
 template <int BW, int NW, bool REV>
-__device__ void block_cyclic_pass(double *line, int n, int k, double p1, double p2, Aff *xchg) {
+__device__ __forceinline__ void block_cyclic_pass(double *line, int n, int k, double p1, double p2, Aff *xchg) {
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int start = min(t * k, n);
@@ -214,15 +189,8 @@ __device__ void block_cyclic_pass(double *line, int n, int k, double p1, double 
 // the current line is being solved, so the copy into LDS rarely waits for
 // memory; longer lines load their remaining elements in further batches.
 // Src::get(li) describes line li: input, output, length and coefficients.
-struct LineRef {
-    const void *in;
-    void *out;
-    int n;
-    double p1, p2, invK;
-};
-
 template <typename TI, typename TO, int BW, int NW, class Src>
-__device__ void solve_lines(const Src &src, int nlines, double *smem) {
+__device__ __forceinline__ void solve_lines(const Src &src, int nlines, double *smem) {
     constexpr int NT = 64 * NW;
     constexpr int U = 32;
     const int t = threadIdx.x;
@@ -231,9 +199,9 @@ __device__ void solve_lines(const Src &src, int nlines, double *smem) {
     // copy into LDS
     TI r[U];
     auto fetch = [&](const LineRef &L, int b0) {
-        const TI *in = static_cast<const TI *>(L.in);
+        const gptr<const TI> in = as_global(static_cast<const TI *>(L.in));
 #pragma unroll
-        for (int u = 0; u < U; ++u) r[u] = in[min(b0 + u * NT + t, L.n - 1)];
+        for (int u = 0; u < U; ++u) r[u] = gld<TI>(in, min(b0 + u * NT + t, L.n - 1));
     };
     int li = blockIdx.x;
     LineRef L{};
@@ -266,47 +234,12 @@ __device__ void solve_lines(const Src &src, int nlines, double *smem) {
         block_cyclic_pass<BW, NW, false>(line, n, k, L.p1, L.p2, xchg);
         block_cyclic_pass<BW, NW, true>(line, n, k, L.p1, L.p2, xchg);
         __syncthreads();
-        TO *out = static_cast<TO *>(L.out);
-        for (int i = t; i < n; i += NT) out[i] = from_f64<TO>(line[lds_pos(i, k, kinv)] * L.invK);
+        const gptr<TO> out = as_global(static_cast<TO *>(L.out));
+        for (int i = t; i < n; i += NT) gst<TO>(out, i, from_f64<TO>(line[lds_pos(i, k, kinv)] * L.invK));
         li = next;
         L = Ln;
     }
 }
-
-template <typename T>
-struct RaggedSrc {
-    RaggedLines a;
-    __device__ LineRef get(int li) const {
-        const int b = a.order[li];
-        const long long base = a.offsets[b];
-        LineRef L;
-        L.in = static_cast<const T *>(a.in) + base;
-        L.out = static_cast<T *>(a.out) + base;
-        L.n = static_cast<int>(a.offsets[b + 1] - base);
-        L.p1 = a.p1;
-        L.p2 = a.p2;
-        L.invK = a.invK;
-        return L;
-    }
-};
-
-template <typename T>
-struct RowsSrc {
-    const RowsInst *inst;
-    const int *map;
-    __device__ LineRef get(int li) const {
-        const RowsInst &I = inst[map ? map[li] : 0];
-        const long long j = li - I.line0;
-        LineRef L;
-        L.in = static_cast<const T *>(I.in) + j * I.ld;
-        L.out = static_cast<T *>(I.out) + j * I.ld;
-        L.n = I.nx;
-        L.p1 = I.p1;
-        L.p2 = I.p2;
-        L.invK = I.invK;
-        return L;
-    }
-};
 
 template <typename T, int BW, int NW>
 __global__ void __launch_bounds__(64 * NW) ragged_lines_kernel(const RaggedLines a) {
@@ -330,13 +263,13 @@ __device__ __forceinline__ int find_inst(const int *map, int blk) { return map ?
 // kSeg rows, so the body has no branch and every load can be in flight at
 // once.
 template <typename TR, int BW, bool FULL>
-__device__ __forceinline__ void seg_a(const TR *rhs, long long ld, int len, double p1, double p2,
+__device__ __forceinline__ void seg_a(gptr<const TR> rhs, long long ld, int len, double p1, double p2,
                                       double &s0, double &s1, double &t0, double &t1) {
     const int n = FULL ? kSeg : len;
     TR raw[kSeg];
 #pragma unroll
     for (int j = 0; j < kSeg; ++j)
-        if (j < n) raw[j] = rhs[static_cast<long long>(j) * ld];
+        if (j < n) raw[j] = gld<TR>(rhs, static_cast<long long>(j) * ld);
     double y[kSeg];
     s0 = s1 = 0.0;
 #pragma unroll
@@ -372,13 +305,13 @@ __global__ void __launch_bounds__(kColsThreads) cols_phase_a(const ColsInst *__r
     if (i >= I.nx) return;
     const int r0 = seg * kSeg;
     const int len = min(kSeg, I.ny - r0);
-    const TR *rhs = static_cast<const TR *>(I.rhs) + static_cast<long long>(r0) * I.ld + i;
+    const gptr<const TR> rhs = as_global(static_cast<const TR *>(I.rhs)) + static_cast<long long>(r0) * I.ld + i;
     double s0, s1, t0, t1;
     if (len == kSeg)
         seg_a<TR, BW, true>(rhs, I.ld, len, I.p1, I.p2, s0, s1, t0, t1);
     else
         seg_a<TR, BW, false>(rhs, I.ld, len, I.p1, I.p2, s0, s1, t0, t1);
-    double *cy = I.carry + static_cast<long long>(seg) * 4 * I.nx + i;
+    const gptr<double> cy = as_global(I.carry) + static_cast<long long>(seg) * 4 * I.nx + i;
     cy[0] = s0;
     cy[I.nx] = s1;
     cy[2 * I.nx] = t0;
@@ -407,7 +340,7 @@ __global__ void __launch_bounds__(kColsThreads) cols_phase_b(const ColsInst *__r
     const int col = (blockIdx.x - I.blkB0) * kBCols + cl;
     const bool valid = col < I.nx;
     const long long nx = I.nx;
-    double *cy = I.carry + (valid ? col : 0);
+    const gptr<double> cy = as_global(I.carry) + (valid ? col : 0);
     const int ns = I.nseg;
     const int sp = (ns + kBGroups - 1) / kBGroups;
     const int sb = min(q * sp, ns), se = min(sb + sp, ns);
@@ -553,14 +486,14 @@ __global__ void __launch_bounds__(kColsThreads) cols_phase_b(const ColsInst *__r
 // output (EPI 1: the Cahn-Hilliard update x = 2 cur - prev + v / K).  FULL as
 // in seg_a.
 template <typename TR, typename TX, int BW, int EPI, bool FULL>
-__device__ __forceinline__ void seg_c(const TR *rhs, TX *x, const TX *cur, const TX *prev,
+__device__ __forceinline__ void seg_c(gptr<const TR> rhs, gptr<TX> x, gptr<const TX> cur, gptr<const TX> prev,
                                       long long ld, int len, double p1, double p2, double invK,
                                       double s0, double s1, double t0, double t1) {
     const int n = FULL ? kSeg : len;
     TR raw[kSeg];
 #pragma unroll
     for (int j = 0; j < kSeg; ++j)
-        if (j < n) raw[j] = rhs[static_cast<long long>(j) * ld];
+        if (j < n) raw[j] = gld<TR>(rhs, static_cast<long long>(j) * ld);
     double y[kSeg];
 #pragma unroll
     for (int j = 0; j < kSeg; ++j) {
@@ -583,7 +516,7 @@ __device__ __forceinline__ void seg_c(const TR *rhs, TX *x, const TX *cur, const
 #pragma unroll
             for (int q = 0; q < G; ++q) {
                 const long long o = static_cast<long long>(jg + q) * ld;
-                if (jg + q < n) cb[q] = 2.0 * to_f64<TX>(cur[o]) - to_f64<TX>(prev[o]);
+                if (jg + q < n) cb[q] = 2.0 * to_f64<TX>(gld<TX>(cur, o)) - to_f64<TX>(gld<TX>(prev, o));
             }
         }
 #pragma unroll
@@ -594,7 +527,7 @@ __device__ __forceinline__ void seg_c(const TR *rhs, TX *x, const TX *cur, const
                 t1 = t0;
                 t0 = v;
                 const long long o = static_cast<long long>(j) * ld;
-                x[o] = from_f64<TX>(EPI == 1 ? cb[q] + v * invK : v * invK);
+                gst<TX>(x, o, from_f64<TX>(EPI == 1 ? cb[q] + v * invK : v * invK));
             }
         }
     }
@@ -613,13 +546,13 @@ __global__ void __launch_bounds__(kColsThreads) cols_phase_c(const ColsInst *__r
     const int r0 = seg * kSeg;
     const int len = min(kSeg, I.ny - r0);
     const long long off = static_cast<long long>(r0) * I.ld + i;
-    const TR *rhs = static_cast<const TR *>(I.rhs) + off;
-    const double *cy = I.carry + static_cast<long long>(seg) * 4 * I.nx + i;
+    const gptr<const TR> rhs = as_global(static_cast<const TR *>(I.rhs)) + off;
+    const gptr<const double> cy = as_global(static_cast<const double *>(I.carry)) + static_cast<long long>(seg) * 4 * I.nx + i;
     const double s0 = cy[0], s1 = cy[I.nx];
     const double t0 = cy[2 * I.nx], t1 = cy[3 * I.nx];
-    TX *x = static_cast<TX *>(I.x) + off;
-    const TX *cur = static_cast<const TX *>(I.cur) + off;
-    const TX *prev = static_cast<const TX *>(I.prev) + off;
+    const gptr<TX> x = as_global(static_cast<TX *>(I.x)) + off;
+    const gptr<const TX> cur = as_global(static_cast<const TX *>(I.cur)) + off;
+    const gptr<const TX> prev = as_global(static_cast<const TX *>(I.prev)) + off;
     if (len == kSeg)
         seg_c<TR, TX, BW, EPI, true>(rhs, x, cur, prev, I.ld, len, I.p1, I.p2, I.invK, s0, s1, t0, t1);
     else

@@ -185,3 +185,23 @@ void fill_cols_coef(const CyclicFactor &f, int bw, int ny, ColsInst *ci) {
 }
 
 }  // namespace mxs
+
+namespace mxs {
+
+void fill_pow_table(const CyclicFactor &f, int bw, double *out) {
+    const ld p1 = f.p1, p2 = bw == 2 ? f.p2 : 0;
+    const M2 M{p1, p2, 1, 0};
+    M2 r{1, 0, 0, 1};
+    for (int k = 0; k <= kWaveBlock; ++k) {
+        store(r, out + 4 * k);
+        r = mul(r, M);
+    }
+    const M2 Mb = mpow(M, kWaveBlock);
+    r = M2{1, 0, 0, 1};
+    for (int c = 0; c <= kWaveNBMax; ++c) {
+        store(r, out + 4 * (kWaveBlock + 1 + c));
+        r = mul(r, Mb);
+    }
+}
+
+}  // namespace mxs

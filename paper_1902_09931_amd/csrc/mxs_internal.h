@@ -8,6 +8,13 @@
 
 namespace mxs {
 
+// Pointers to global memory.  A pointer read from an instance table in
+// device memory is generic (its accesses would be flat instructions, which
+// also occupy the LDS counter); converted with as_global, its accesses are
+// global loads and stores, or scalar loads where uniform.
+template <typename T> using gptr = T __attribute__((address_space(1))) *;
+template <typename T> __device__ __forceinline__ gptr<T> as_global(T *p) { return (gptr<T>)p; }
+
 // ---------------------------------------------------------------------------
 // Storage types.  bfloat16 is carried as its 16 raw bits.
 // ---------------------------------------------------------------------------
@@ -109,6 +116,72 @@ __device__ __forceinline__ void store_vec_nt<bf16>(bf16 *p, const float *x) {
     v2u_t v = {static_cast<uint32_t>(float_to_bf16(x[0])) | (static_cast<uint32_t>(float_to_bf16(x[1])) << 16),
                static_cast<uint32_t>(float_to_bf16(x[2])) | (static_cast<uint32_t>(float_to_bf16(x[3])) << 16)};
     __builtin_nontemporal_store(v, reinterpret_cast<v2u_t *>(p));
+}
+
+// Element access through global-memory pointers (bf16 by its bits).
+template <typename T> __device__ __forceinline__ T gld(gptr<const T> p, long long i) { return p[i]; }
+template <> __device__ __forceinline__ bf16 gld<bf16>(gptr<const bf16> p, long long i) {
+    return bf16{reinterpret_cast<gptr<const uint16_t>>(p)[i]};
+}
+template <typename T> __device__ __forceinline__ void gst(gptr<T> p, long long i, T v) { p[i] = v; }
+template <> __device__ __forceinline__ void gst<bf16>(gptr<bf16> p, long long i, bf16 v) {
+    reinterpret_cast<gptr<uint16_t>>(p)[i] = v.bits;
+}
+
+// The same vector accesses through global-memory pointers.
+template <typename T>
+__device__ __forceinline__ void load_vec(gptr<const T> p, typename St<T>::acc *x);
+template <>
+__device__ __forceinline__ void load_vec<double>(gptr<const double> p, double *x) {
+    const v2d_t v = *reinterpret_cast<gptr<const v2d_t>>(p);
+    x[0] = v.x; x[1] = v.y;
+}
+template <>
+__device__ __forceinline__ void load_vec<float>(gptr<const float> p, float *x) {
+    const v4f_t v = *reinterpret_cast<gptr<const v4f_t>>(p);
+    x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void load_vec<bf16>(gptr<const bf16> p, float *x) {
+    const v2u_t v = *reinterpret_cast<gptr<const v2u_t>>(p);
+    x[0] = __uint_as_float(v.x << 16); x[1] = __uint_as_float(v.x & 0xffff0000u);
+    x[2] = __uint_as_float(v.y << 16); x[3] = __uint_as_float(v.y & 0xffff0000u);
+}
+template <typename T>
+__device__ __forceinline__ void store_vec(gptr<T> p, const typename St<T>::acc *x);
+template <>
+__device__ __forceinline__ void store_vec<double>(gptr<double> p, const double *x) {
+    const v2d_t v = {x[0], x[1]};
+    *reinterpret_cast<gptr<v2d_t>>(p) = v;
+}
+template <>
+__device__ __forceinline__ void store_vec<float>(gptr<float> p, const float *x) {
+    const v4f_t v = {x[0], x[1], x[2], x[3]};
+    *reinterpret_cast<gptr<v4f_t>>(p) = v;
+}
+template <>
+__device__ __forceinline__ void store_vec<bf16>(gptr<bf16> p, const float *x) {
+    const v2u_t v = {static_cast<uint32_t>(float_to_bf16(x[0])) | (static_cast<uint32_t>(float_to_bf16(x[1])) << 16),
+                     static_cast<uint32_t>(float_to_bf16(x[2])) | (static_cast<uint32_t>(float_to_bf16(x[3])) << 16)};
+    *reinterpret_cast<gptr<v2u_t>>(p) = v;
+}
+template <typename T>
+__device__ __forceinline__ void store_vec_nt(gptr<T> p, const typename St<T>::acc *x);
+template <>
+__device__ __forceinline__ void store_vec_nt<double>(gptr<double> p, const double *x) {
+    v2d_t v = {x[0], x[1]};
+    __builtin_nontemporal_store(v, reinterpret_cast<gptr<v2d_t>>(p));
+}
+template <>
+__device__ __forceinline__ void store_vec_nt<float>(gptr<float> p, const float *x) {
+    v4f_t v = {x[0], x[1], x[2], x[3]};
+    __builtin_nontemporal_store(v, reinterpret_cast<gptr<v4f_t>>(p));
+}
+template <>
+__device__ __forceinline__ void store_vec_nt<bf16>(gptr<bf16> p, const float *x) {
+    v2u_t v = {static_cast<uint32_t>(float_to_bf16(x[0])) | (static_cast<uint32_t>(float_to_bf16(x[1])) << 16),
+               static_cast<uint32_t>(float_to_bf16(x[2])) | (static_cast<uint32_t>(float_to_bf16(x[3])) << 16)};
+    __builtin_nontemporal_store(v, reinterpret_cast<gptr<v2u_t>>(p));
 }
 
 __device__ __forceinline__ long long wrap_ll(long long k, long long n) {

@@ -43,6 +43,29 @@ inline size_t line_lds_bytes(long long nmax, int nw) {
     return (static_cast<size_t>(64) * nw * (line_chunk(nmax, nw) + 1) + 6 * nw) * sizeof(double);
 }
 
+// --- lines held in the registers of one wavefront -----------------------------
+// A line of at most kWaveLineMax elements is held by one wavefront: blocks of
+// kWaveBlock elements, 4 consecutive elements per lane.  Each block is
+// scanned across the lanes with powers of the companion matrix
+// M = [[p1, p2], [1, 0]] taken from a table: entries k = 0..kWaveBlock hold
+// M^k, entries kWaveBlock + 1 + c hold M^(kWaveBlock c), c = 0..kWaveNBMax;
+// each entry is 4 doubles, row-major.
+constexpr int kWaveBlock = 256;
+constexpr int kWaveNBMax = 16;
+constexpr int kWaveLineMax = kWaveBlock * kWaveNBMax;
+constexpr int kPowEntries = kWaveBlock + 1 + kWaveNBMax + 1;
+void fill_pow_table(const CyclicFactor &f, int bw, double *out);   // 4 * kPowEntries doubles
+// Register blocks of the kernel that holds a line of n elements (n <= kWaveLineMax).
+inline int wave_nb(long long n) {
+    const long long nb = (n + kWaveBlock - 1) / kWaveBlock;
+    return nb <= 2 ? 2 : nb <= 4 ? 4 : nb <= 8 ? 8 : 16;
+}
+// The LDS kernel is used for every line when MXS_LINE_KERNEL=lds (tests).
+inline bool force_lds_lines() {
+    const char *env = getenv("MXS_LINE_KERNEL");
+    return env && env[0] == 'l';
+}
+
 // --- lines solved by one workgroup each --------------------------------------
 struct RaggedLines {
     const void *in;
@@ -51,6 +74,7 @@ struct RaggedLines {
     const int *order;           // device, lines by decreasing length
     int nlines;
     double p1, p2, invK;
+    const double *pow;          // power table (register kernel)
 };
 
 struct RowsInst {
@@ -60,6 +84,7 @@ struct RowsInst {
     int nx, ny;
     int line0;                  // first global line index of this instance
     double p1, p2, invK;
+    const double *pow;          // power table (register kernel)
 };
 
 // --- columns: three phases over segments of kSeg rows -------------------------
@@ -95,6 +120,12 @@ hipError_t launch_ragged_lines(int dtype, int bw, const RaggedLines &a, int nw, 
 // belong to instance 0.
 hipError_t launch_rows(int dtype, int bw, const RowsInst *inst, const int *map, int nlines, int nw,
                        int grid, size_t lds, hipStream_t s);
+// Register kernel over lines first .. first + count - 1 (sorted positions for
+// ragged lines, global line indices for rows), each at most 256 nb elements.
+hipError_t launch_wave_ragged(int dtype, int bw, int nb, const RaggedLines &a, int first, int count,
+                              hipStream_t s);
+hipError_t launch_wave_rows(int dtype, int bw, int nb, const RowsInst *inst, const int *map, int first,
+                            int count, hipStream_t s);
 // epilogue: 0 = x = A^-1 rhs; 1 = Cahn-Hilliard update x = 2 cur - prev + A^-1 rhs.
 // (rhs dtype, output dtype) pairs: (F64,F64), (F32,F32), (BF16,BF16), (F32,BF16).
 hipError_t launch_cols(int rhs_dtype, int x_dtype, int bw, int epilogue, const ColsInst *inst,

@@ -36,7 +36,15 @@ struct SolvePlan final : mxs_plan_s {
     // rows / cols
     RowsInst rows{};
     ColsInst cols{};
-    DevBuf table, carry;
+    DevBuf table, carry, pow;
+    // register kernel: (blocks per line, first line, line count) per class;
+    // ragged lines longer than kWaveLineMax (the first nlong in sorted
+    // order) go to the LDS kernel
+    struct WaveRange {
+        int nb, first, count;
+    };
+    std::vector<WaveRange> wave;
+    int nlong = 0;
     int nlines = 0, grid = 1, blocksAC = 0, blocksB = 0, nw = 1;
     size_t lds = 0, bytes = 0;
     bool dirty = true;
@@ -59,15 +67,19 @@ struct SolvePlan final : mxs_plan_s {
     mxs_status compute(hipStream_t s) override {
         hipError_t e = hipSuccess;
         if (geometry == MXS_LINES_RAGGED) {
-            e = launch_ragged_lines(dtype, bw, rl, nw, grid, lds, s);
+            if (nlong > 0) e = launch_ragged_lines(dtype, bw, rl, nw, grid, lds, s);
+            for (size_t q = 0; q < wave.size() && e == hipSuccess; ++q)
+                e = launch_wave_ragged(dtype, bw, wave[q].nb, rl, wave[q].first, wave[q].count, s);
         } else if (geometry == MXS_LINES_ROWS) {
             if (dirty) {
                 e = hipMemcpyAsync(table.ptr, &rows, sizeof rows, hipMemcpyHostToDevice, s);
                 dirty = false;
             }
-            if (e == hipSuccess)
-                e = launch_rows(dtype, bw, static_cast<const RowsInst *>(table.ptr), nullptr, nlines,
-                                nw, grid, lds, s);
+            const RowsInst *ti = static_cast<const RowsInst *>(table.ptr);
+            if (e == hipSuccess && !wave.empty())
+                e = launch_wave_rows(dtype, bw, wave[0].nb, ti, nullptr, 0, nlines, s);
+            else if (e == hipSuccess)
+                e = launch_rows(dtype, bw, ti, nullptr, nlines, nw, grid, lds, s);
         } else {
             if (dirty) {
                 e = hipMemcpyAsync(table.ptr, &cols, sizeof cols, hipMemcpyHostToDevice, s);
@@ -90,13 +102,15 @@ struct SolvePlan final : mxs_plan_s {
     void set_waves(int w) {
         nw = w;
         lds = line_lds_bytes(nmax, nw);
-        grid = wave_grid(geometry == MXS_LINES_RAGGED ? rl.nlines : nlines, lds);
+        grid = wave_grid(std::max(1, geometry == MXS_LINES_RAGGED ? nlong : nlines), lds);
     }
 
     // Wavefronts per line: one (long chunks, few barriers) to four (more
     // loads in flight per line); chosen by timing.
     mxs_status autotune(hipStream_t s) override {
-        if (geometry == MXS_LINES_COLS) return MXS_OK;
+        // only the LDS kernel has a shape to choose
+        if (geometry == MXS_LINES_COLS || (geometry == MXS_LINES_RAGGED ? nlong == 0 : !wave.empty()))
+            return MXS_OK;
         const int start = nw;
         int best = nw;
         double best_t = 1e30;
@@ -119,8 +133,13 @@ struct SolvePlan final : mxs_plan_s {
         return MXS_OK;
     }
     void info(char *buf, int len) const override {
-        snprintf(buf, len, "cyclic_solve geometry=%d bw=%d dtype=%d waves_per_line=%d grid=%d lds=%zu",
-                 geometry, bw, dtype, nw, grid, lds);
+        int n = snprintf(buf, len, "cyclic_solve geometry=%d bw=%d dtype=%d", geometry, bw, dtype);
+        const bool lds_kernel = geometry == MXS_LINES_RAGGED ? nlong > 0 : wave.empty();
+        if (geometry != MXS_LINES_COLS && lds_kernel && n < len)
+            n += snprintf(buf + n, len - n, " lds_kernel_lines=%d waves_per_line=%d grid=%d lds=%zu",
+                          geometry == MXS_LINES_RAGGED ? nlong : nlines, nw, grid, lds);
+        for (size_t q = 0; q < wave.size() && n < len; ++q)
+            n += snprintf(buf + n, len - n, " register_kernel(nb=%d lines=%d)", wave[q].nb, wave[q].count);
     }
 };
 
@@ -156,6 +175,16 @@ extern "C" mxs_status mxs_create_cyclic_solve(int bw, const double *coef, int ge
     }
     mxs_status st;
     hipError_t e = hipSuccess;
+    if (geometry != MXS_LINES_COLS) {
+        std::vector<double> pt(4 * kPowEntries);
+        fill_pow_table(p->f, bw, pt.data());
+        if ((e = p->pow.upload(pt.data(), sizeof(double) * pt.size())) != hipSuccess) {
+            delete p;
+            return hip_fail(e, "power table upload");
+        }
+        p->rl.pow = static_cast<const double *>(p->pow.ptr);
+        p->rows.pow = p->rl.pow;
+    }
     if (geometry == MXS_LINES_RAGGED) {
         if (nbatch <= 0 || !offsets) {
             delete p;
@@ -189,9 +218,24 @@ extern "C" mxs_status mxs_create_cyclic_solve(int bw, const double *coef, int ge
             delete p;
             return hip_fail(e, "line tables upload");
         }
+        // lines longer than kWaveLineMax to the LDS kernel, the rest by
+        // register-block class (lengths are sorted, so classes are ranges)
+        p->nlong = 0;
+        if (force_lds_lines()) {
+            p->nlong = nbatch;
+        } else {
+            while (p->nlong < nbatch && len[order[p->nlong]] > kWaveLineMax) ++p->nlong;
+            for (int q = p->nlong; q < nbatch;) {
+                const int nb = wave_nb(len[order[q]]);
+                int r = q;
+                while (r < nbatch && wave_nb(len[order[r]]) == nb) ++r;
+                p->wave.push_back({nb, q, r - q});
+                q = r;
+            }
+        }
         p->rl.offsets = static_cast<const long long *>(p->offsets.ptr);
         p->rl.order = static_cast<const int *>(p->order.ptr);
-        p->rl.nlines = nbatch;
+        p->rl.nlines = p->nlong;
         p->rl.p1 = p->f.p1;
         p->rl.p2 = bw == 2 ? p->f.p2 : 0.0;
         p->rl.invK = p->f.invK;
@@ -223,6 +267,7 @@ extern "C" mxs_status mxs_create_cyclic_solve(int bw, const double *coef, int ge
             p->rows.invK = p->f.invK;
             p->nlines = ny;
             p->nmax = nx;
+            if (nx <= kWaveLineMax && !force_lds_lines()) p->wave.push_back({wave_nb(nx), 0, ny});
             p->set_waves(line_waves(nx));
             e = p->table.alloc(sizeof(RowsInst));
         } else {

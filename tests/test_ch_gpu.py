@@ -70,6 +70,23 @@ def test_ch_small_grids_f64(shape, use_graph):
         g.close()
 
 
+def test_ch_lds_row_kernel(monkeypatch):
+    """The LDS row kernel (forced) gives the same step as the oracle."""
+    monkeypatch.setenv("MXS_LINE_KERNEL", "lds")
+    c0 = wl.ch_initial(48, 80, seed=3)
+    g = Grid(c0)
+    try:
+        assert "row_kernel=lds" in b.mxs_plan_info(g.plan)
+        b.mxs_ch_step(g.plan, 20, True)
+        torch.cuda.synchronize()
+        gp, gc = g.state()
+    finally:
+        g.close()
+    op, oc = oracle.ch_run(c0, c0, 20, g.dx, g.dy, g.dt, D, GAMMA)
+    assert rel_err(gc, oc) <= 1e-12
+    assert rel_err(gp, op) <= 1e-12
+
+
 def test_ch_first_step_spectral_closed_form():
     """The GPU step against the closed form of one step from
     C^{-1} = C^0 = A cos(kx) cos(ly) (independent of the oracle)."""
@@ -179,7 +196,7 @@ def test_ch_reduced_precision_error(dt_name, bound):
 def test_ch_ensemble_matches_single_grids_and_oracle():
     """An ensemble of grids of mixed sizes advances as the separate grids do
     (bit-identical), and matches the oracle per instance."""
-    sizes = [(64, 64), (96, 96), (40, 72), (128, 128), (64, 64)]
+    sizes = [(64, 64), (96, 96), (40, 600), (128, 128), (24, 1100), (40, 72), (64, 64)]
     c0s = [wl.ch_initial(ny, nx, seed=10 + k) for k, (ny, nx) in enumerate(sizes)]
     nsteps = 20
     bufs = []
@@ -241,7 +258,7 @@ def test_autotune_keeps_the_state_and_parity():
         torch.cuda.synchronize()
         before = g.state()
         b.mxs_autotune(g.plan)
-        assert "row_waves=" in b.mxs_plan_info(g.plan)
+        assert "rhs_rows=" in b.mxs_plan_info(g.plan)
         assert b.mxs_ch_steps_taken(g.plan) == 2
         after = g.state()
         assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])

@@ -139,7 +139,9 @@ def test_solve_argument_errors():
 
 @pytest.mark.parametrize("waves", ["1", "2", "4"])
 def test_every_line_workgroup_shape(monkeypatch, waves):
-    """One, two or four wavefronts per line give the same solution."""
+    """The LDS kernel with one, two or four wavefronts per line gives the
+    same solution."""
+    monkeypatch.setenv("MXS_LINE_KERNEL", "lds")
     monkeypatch.setenv("MXS_LINE_WAVES", waves)
     rng = np.random.default_rng(31)
     lengths = rng.permutation([5, 64, 65, 129, 1000, 4096, 3001, 2048, 17])
@@ -167,3 +169,56 @@ def test_autotuned_solve_keeps_parity():
     torch.cuda.synchronize()
     b.mxs_destroy(p)
     check(to_host(dx), oracle.cyclic_solve_grid(oracle.circulant_bands(TRI), 1, r), "f64")
+
+
+# every register class (256, 512, 1024, 2048, 4096 elements), block edges,
+# partial lanes, and lines longer than the register kernel holds
+CLASS_LENGTHS = [5, 6, 7, 63, 64, 65, 255, 256, 257, 259, 511, 512, 513, 1000, 1023, 1025,
+                 2047, 2048, 2049, 3001, 4093, 4095, 4096, 4097, 6000, 9001]
+
+
+@pytest.mark.parametrize("kernel", ["register", "lds"])
+@pytest.mark.parametrize("coef", [TRI, PENTA, OTHER])
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+def test_line_kernels_every_length_class(monkeypatch, kernel, coef, dt):
+    if kernel == "lds":
+        monkeypatch.setenv("MXS_LINE_KERNEL", "lds")
+    bw = len(coef) - 1
+    rng = np.random.default_rng(41 + bw)
+    lengths = rng.permutation(CLASS_LENGTHS)
+    offs = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    r = rng.uniform(-1, 1, offs[-1])
+    rr = round_to(r, dt)
+    drhs = to_device(r, dt)
+    dx = torch.empty_like(drhs)
+    p = b.mxs_create_cyclic_solve(bw, coef, b.MXS_LINES_RAGGED, 0, 0, 0, offs, code(dt), drhs, dx)
+    info = b.mxs_plan_info(p)
+    if kernel == "lds":
+        assert "register_kernel" not in info
+    else:
+        for nb in (2, 4, 8, 16):
+            assert f"register_kernel(nb={nb}" in info
+        assert "lds_kernel_lines=3 " in info     # 4097, 6000 and 9001
+    b.mxs_compute(p)
+    torch.cuda.synchronize()
+    b.mxs_destroy(p)
+    ref = oracle.cyclic_solve_batch(oracle.circulant_bands(coef), offs, rr)
+    check(dx.double().cpu().numpy(), ref, dt)
+
+
+@pytest.mark.parametrize("kernel", ["register", "lds"])
+@pytest.mark.parametrize("nx", [5, 200, 256, 700, 1024, 1500, 4096])
+def test_row_kernels(monkeypatch, kernel, nx):
+    if kernel == "lds":
+        monkeypatch.setenv("MXS_LINE_KERNEL", "lds")
+    ny = 37
+    rng = np.random.default_rng(nx)
+    r = rng.uniform(-1, 1, (ny, nx))
+    drhs = to_device(r, "f64")
+    dx = torch.empty_like(drhs)
+    p = b.mxs_create_cyclic_solve(2, PENTA_SMALL, b.MXS_LINES_ROWS, nx, ny, nx, None, b.MXS_F64, drhs, dx)
+    assert ("register_kernel" in b.mxs_plan_info(p)) == (kernel == "register")
+    b.mxs_compute(p)
+    torch.cuda.synchronize()
+    b.mxs_destroy(p)
+    check(to_host(dx), oracle.cyclic_solve_grid(oracle.circulant_bands(PENTA_SMALL), 1, r), "f64")
