@@ -119,13 +119,13 @@ __device__ __forceinline__ void store_vec_nt<bf16>(bf16 *p, const float *x) {
 }
 
 // Element access through global-memory pointers (bf16 by its bits).
-template <typename T> __device__ __forceinline__ T gld(gptr<const T> p, long long i) { return p[i]; }
-template <> __device__ __forceinline__ bf16 gld<bf16>(gptr<const bf16> p, long long i) {
-    return bf16{reinterpret_cast<gptr<const uint16_t>>(p)[i]};
+template <typename T, typename I> __device__ __forceinline__ T gld(gptr<const T> p, I i) {
+    if constexpr (std::is_same<T, bf16>::value) return bf16{reinterpret_cast<gptr<const uint16_t>>(p)[i]};
+    else return p[i];
 }
-template <typename T> __device__ __forceinline__ void gst(gptr<T> p, long long i, T v) { p[i] = v; }
-template <> __device__ __forceinline__ void gst<bf16>(gptr<bf16> p, long long i, bf16 v) {
-    reinterpret_cast<gptr<uint16_t>>(p)[i] = v.bits;
+template <typename T, typename I> __device__ __forceinline__ void gst(gptr<T> p, I i, T v) {
+    if constexpr (std::is_same<T, bf16>::value) reinterpret_cast<gptr<uint16_t>>(p)[i] = v.bits;
+    else p[i] = v;
 }
 
 // The same vector accesses through global-memory pointers.

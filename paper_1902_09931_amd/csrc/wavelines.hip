@@ -196,11 +196,18 @@ __device__ __forceinline__ void wave_line(const Src &src, int li) {
     // every element of the line requested before any is used
     const gptr<const TI> in = as_global(static_cast<const TI *>(L.in));
     TI raw[4 * NB];
+    // (per-lane 32-bit offsets from the uniform line base; only the last
+    // block is clamped into the line)
+    const unsigned lo = 4u * lane;
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
-        if (c < nblk) {
+        if (c < last) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) raw[4 * c + j] = gld<TI>(in, min(B * c + 4 * lane + j, n - 1));
+            for (int j = 0; j < 4; ++j) raw[4 * c + j] = gld<TI>(in, lo + static_cast<unsigned>(B * c + j));
+        } else if (c == last) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                raw[4 * c + j] = gld<TI>(in, min(static_cast<int>(lo) + B * c + j, n - 1));
         }
     }
     Powers P;
@@ -222,15 +229,21 @@ __device__ __forceinline__ void wave_line(const Src &src, int li) {
     S2 F{0.0, 0.0};
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
-        if (c < nblk) {
+        if (c < last) {
+            double r[4], v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) r[j] = to_f64<TI>(raw[4 * c + j]);
+            F = block_forward<BW>(r, v, P, Mp, row, F, p1, p2);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) y[4 * c + j] = v[j];
+        } else if (c == last) {
             const int i0 = B * c + 4 * lane;
             double r[4], v[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) r[j] = i0 + j < n ? to_f64<TI>(raw[4 * c + j]) : 0.0;
-            const S2 T = block_forward<BW>(r, v, P, Mp, row, F, p1, p2);
+            (void)block_forward<BW>(r, v, P, Mp, row, F, p1, p2);
 #pragma unroll
             for (int j = 0; j < 4; ++j) y[4 * c + j] = v[j];
-            if (c < last) F = T;
         }
     }
     // state after element n - 1, read from the values of the last block
@@ -257,12 +270,17 @@ __device__ __forceinline__ void wave_line(const Src &src, int li) {
     S2 G{0.0, 0.0};
 #pragma unroll
     for (int c = NB - 1; c >= 0; --c) {
-        if (c < nblk) {
-            const int i0 = B * c + 4 * lane;
+        if (c <= last) {
             const S2 w = mv<BW>(Mp, by_row<BW>(row, m64r, mv<BW>(load_mat(pb + 4 * c), x0)));
             double r[4], v[4];
+            if (c == last) {
+                const int i0 = B * c + 4 * lane;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) r[j] = i0 + j < n ? y[4 * c + j] + row0<BW>(P.e[j + 1], w) : 0.0;
+                for (int j = 0; j < 4; ++j) r[j] = i0 + j < n ? y[4 * c + j] + row0<BW>(P.e[j + 1], w) : 0.0;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) r[j] = y[4 * c + j] + row0<BW>(P.e[j + 1], w);
+            }
             G = block_backward<BW>(r, v, P, Mq, row, G, p1, p2);
 #pragma unroll
             for (int j = 0; j < 4; ++j) y[4 * c + j] = v[j];
@@ -279,10 +297,10 @@ __device__ __forceinline__ void wave_line(const Src &src, int li) {
             // n - i = len_last + B (last - 1 - c) + 64 (3 - row) + 4 (15 - p) + (4 - j)
             const S2 u = mv<BW>(Mlen, mv<BW>(load_mat(pb + 4 * (last - 1 - c)), z0));
             const S2 w = mv<BW>(Mq, by_row<BW>(3 - row, m64r, u));
-            const int i0 = B * c + 4 * lane;
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                gst<TO>(out, i0 + j, from_f64<TO>((y[4 * c + j] + row0<BW>(P.e[4 - j], w)) * invK));
+                gst<TO>(out, lo + static_cast<unsigned>(B * c + j),
+                        from_f64<TO>((y[4 * c + j] + row0<BW>(P.e[4 - j], w)) * invK));
         } else if (c == last) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
