@@ -20,12 +20,23 @@ ADI Cahn-Hilliard step on 1024^2 and 4096^2 FP64 grids (steps/s), the
 Only the cpu_baseline leg uses the oracle.
 """
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
 import time
 
+HERE = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of the 8192^2 FP64 stencil kernels from rocprofv3 counters
+# (FETCH_SIZE, WRITE_SIZE), valid while the kernel sources and the tile
+# layout are the ones it was taken with.
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "stencil2d_8192_f64_traffic.json")
+TRAFFIC_SOURCES = ["paper_1902_09931_amd/csrc/stencil2d.hip", "paper_1902_09931_amd/csrc/mxs_internal.h"]
+# tile layouts (rows, order, threads, streaming stores) used by the counter runs
+PROFILE_LAYOUTS = "x=4,1,256,1;y=64,1,128,1;xy=16,1,256,1;fun=16,1,256,1"
 METRIC = "stencil Gpoints/s + % HBM peak; CH ADI steps/s (FP64 vs FP32/batched)"
 
 
@@ -85,6 +96,8 @@ def bench_stencil_set(torch, b, wl, n, dt, steps, warmup):
             layouts[key] = b.mxs_plan_info(ps[0])
             plans.append((key, ps))
     counter = [0]
+    # marker for kernel traces: the launches after this fill are the timed ones
+    torch.ones(1, device="cuda").fill_(3.0)
 
     def step():
         for _, ps in plans:
@@ -109,6 +122,101 @@ def bench_stencil_set(torch, b, wl, n, dt, steps, warmup):
     del ins, outs, u0
     torch.cuda.empty_cache()
     return sec / steps, wall / steps, per_kernel, len(plans), layouts
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profile_stencils(torch, b, wl, n, layouts):
+    """Workload for counter runs: the eight stencils of the set with fixed
+    tile layouts, then a marker fill, two launches of each stencil in set
+    order, and two copies of 512 MiB (the counters' calibration)."""
+    lay = dict(kv.split("=") for kv in layouts.split(";"))
+    kind = {"x_d2_4th": "x", "y_d2_4th": "y", "xy_cross_fig1": "xy", "lap_cubic_fun": "fun"}
+    u = torch.from_numpy(wl.uniform_grid(n, n, seed=1)).cuda()
+    out = torch.zeros_like(u)
+    dirs = {"X": b.MXS_X, "Y": b.MXS_Y, "XY": b.MXS_XY}
+    plans = []
+    for name, d, ext, w, coe in stencil_set(wl, 1.0 / n):
+        for periodic in (True, False):
+            os.environ["MXS_STENCIL_TILE"] = lay[kind[name]]
+            p = b.mxs_create_2d(n, n, n, dirs[d], b.MXS_P if periodic else b.MXS_NP, b.MXS_F64,
+                                *ext, w, coe, u, out)
+            plans.append((f"{name}_{'p' if periodic else 'np'}", p))
+    os.environ.pop("MXS_STENCIL_TILE", None)
+    for _, p in plans:
+        b.mxs_compute(p)
+    torch.cuda.synchronize()
+    torch.ones(1, device="cuda").fill_(2.0)      # marker
+    for _, p in plans:
+        for _ in range(2):
+            b.mxs_compute(p)
+    a = torch.empty(1 << 26, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    for _ in range(2):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_order": [k for k, _ in plans],
+                      "layouts": {k: b.mxs_plan_info(p) for k, p in plans}}), flush=True)
+    for _, p in plans:
+        b.mxs_destroy(p)
+
+
+def traffic_summary(fetch_dir, write_dir, layouts_json):
+    """Turn the two counter runs of profile_stencils into per-launch HBM bytes
+    of each stencil kernel, scaled by what the counters read for the 512 MiB
+    copies; writes TRAFFIC_FILE and prints a markdown table."""
+    def dispatches(d):
+        rows = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                k = int(r["Dispatch_Id"])
+                rows.setdefault(k, [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
+        ks = sorted(rows)
+        m = max(i for i, k in enumerate(ks) if "FillFunctor" in rows[k][0])
+        return [rows[k] for k in ks[m + 1:]]
+    info = json.loads([ln for ln in open(layouts_json) if ln.startswith("{")][-1])
+    order, layouts = info["profile_order"], info["layouts"]
+    fe, wr = dispatches(fetch_dir), dispatches(write_dir)
+    ns = 2 * len(order)
+    copy_bytes = float(8 << 26)
+    fetch_scale = copy_bytes / (sum(v for _, v in fe[ns:ns + 2]) / 2 * 1024)
+    write_scale = copy_bytes / (sum(v for _, v in wr[ns:ns + 2]) / 2 * 1024)
+    kern = {}
+    for i, name in enumerate(order):
+        fk = (fe[2 * i][1] + fe[2 * i + 1][1]) / 2
+        wk = (wr[2 * i][1] + wr[2 * i + 1][1]) / 2
+        kern[name] = {"layout": layouts[name], "fetch_kib": fk, "write_kib": wk,
+                      "bytes": fk * 1024 * fetch_scale + wk * 1024 * write_scale}
+    out = {"digest": source_digest(), "workload": "8192x8192 FP64 stencil set",
+           "fetch_scale": fetch_scale, "write_scale": write_scale,
+           "algorithmic_bytes_per_launch": 2 * 8 * 8192 * 8192, "kernels": kern}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(f"copy calibration: FETCH_SIZE x {fetch_scale:.3f}, WRITE_SIZE x {write_scale:.3f}\n")
+    print("| stencil | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | HBM bytes (scaled) | / algorithmic |")
+    print("|---|---:|---:|---:|---:|")
+    for name, k in kern.items():
+        print(f"| {name} | {k['fetch_kib']:.0f} | {k['write_kib']:.0f} | {k['bytes']:.4g} | "
+              f"{k['bytes'] / out['algorithmic_bytes_per_launch']:.3f} |")
+
+
+def measured_traffic(kernel, layout):
+    """HBM bytes per launch of a stencil kernel from the committed counter
+    summary, or None when the sources or the layout differ from it."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    if t.get("digest") != source_digest() or not k or k.get("layout") != layout:
+        return None
+    return k["bytes"]
 
 
 def bench_ragged_1d(torch, b, wl, dt, steps, warmup):
@@ -255,11 +363,20 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--sections-only", action="store_true",
+                    help="skip the headline stencil set (for profiling the sections)")
     ap.add_argument("--sections", default="f32,ragged,tri,ch,ensemble,copy",
                     help="extra sections to run (comma list)")
     ap.add_argument("--ch-steps", type=int, default=0,
                     help="override the Cahn-Hilliard step counts (0: 1000 at 1024^2, 200 at 4096^2)")
+    ap.add_argument("--profile-stencils", nargs="?", const=PROFILE_LAYOUTS, default=None,
+                    metavar="LAYOUTS", help="run the counter workload for the stencil set only")
+    ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "LAYOUTS_JSON"),
+                    help="summarise the two counter runs (no GPU needed)")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary)
+        return
     sections = set(args.sections.split(",")) if not args.no_extra else set()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -271,9 +388,17 @@ def main():
     from paper_1902_09931_amd import workloads as wl
 
     n = args.n
+    if args.profile_stencils:
+        profile_stencils(torch, b, wl, n, args.profile_stencils)
+        return
     log(f"device {torch.cuda.get_device_name(0)}; stencil set {n}^2 f64")
-    sec, wall, per_kernel, napps, layouts = bench_stencil_set(torch, b, wl, n, "f64", args.steps,
-                                                              args.warmup)
+    if args.sections_only:
+        sec, wall, napps, layouts = 1.0, 1.0, 8, {}
+        per_kernel = {"none": 1.0}
+        layouts["none"] = ""
+    else:
+        sec, wall, per_kernel, napps, layouts = bench_stencil_set(torch, b, wl, n, "f64", args.steps,
+                                                                  args.warmup)
     pts = napps * n * n
     dominant = max(per_kernel, key=per_kernel.get)
     bytes_per_launch = 2 * 8 * n * n
@@ -296,7 +421,8 @@ def main():
                                "5-point Laplacian of c^3-c; periodic and non-periodic",
                    "grid": [n, n], "stencil_applications_per_step": napps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dominant, layouts[dominant]) if n == 8192 else None,
                      "kernel": dominant, "avg_launch_us": per_kernel[dominant] * 1e6,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }

@@ -13,6 +13,15 @@ import os
 
 import numpy as np
 
+# torch (ROCm) ships its own copy of the HIP runtime under the same soname
+# as the system one.  Loading torch first makes the library bind to that
+# copy, so that torch's tensors and the library's kernels share one runtime;
+# loaded the other way round, the process would hold two runtimes.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _LIBPATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmxsten.so")
 if not os.path.exists(_LIBPATH):
     raise ImportError(f"{_LIBPATH} is missing: build it with `python -m paper_1902_09931_amd.build`")

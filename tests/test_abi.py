@@ -82,3 +82,13 @@ def test_create_1d_batch_validation():
     with pytest.raises(b.MxsError) as e:
         b.mxs_create_1d_batch([0, 100], b.MXS_P, b.MXS_F64, 1, 1, [1.0] * 3, None, FAKE_IN, FAKE_IN + 64)
     assert e.value.status == b.MXS_ERR_ALIAS
+
+
+def test_one_hip_runtime_in_the_process():
+    """torch carries its own HIP runtime under the system soname; the binding
+    loads torch first so that the library binds to the same copy (two
+    runtimes in one process do not see each other's device state)."""
+    import torch  # noqa: F401
+    with open("/proc/self/maps") as f:
+        libs = {ln.split()[-1] for ln in f if "libamdhip64" in ln}
+    assert len(libs) == 1, libs
