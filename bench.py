@@ -460,6 +460,8 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(wl, n, rows=min(n, 3072))
+    if args.sections_only:     # no headline was measured: report the sections alone
+        result = {"sections_only": True, "extra": extra}
     print(json.dumps(result), flush=True)
 
 
