@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "stencil2d_8192_f64_traffic.json")
 TRAFFIC_SOURCES = ["paper_1902_09931_amd/csrc/stencil2d.hip", "paper_1902_09931_amd/csrc/mxs_internal.h"]
 # tile layouts (rows, order, threads, streaming stores) used by the counter runs
-PROFILE_LAYOUTS = "x=4,1,256,1;y=64,1,128,1;xy=16,1,256,1;fun=16,1,256,1"
+PROFILE_LAYOUTS = "x=4,1,256,1;y=16,1,256,1;xy=16,1,256,1;fun=16,1,256,1"
 METRIC = "stencil Gpoints/s + % HBM peak; CH ADI steps/s (FP64 vs FP32/batched)"
 
 

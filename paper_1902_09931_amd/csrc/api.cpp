@@ -122,13 +122,19 @@ bool vec_aligned(const void *p, int dtype) {
     return reinterpret_cast<uintptr_t>(p) % bytes == 0;
 }
 
-// Padded weights NWY x NWX in the accumulation type.
+// Padded weights NWY x NWX in the accumulation type, followed by the same
+// window flipped vertically (row q holds window row T + B - q): the kernel
+// reads the second copy for row chunks it walks upward.
 template <typename A>
 std::vector<A> pad_weights(const double *w, int L, int R, int T, int B, int nwx, int nwy) {
-    std::vector<A> out(static_cast<size_t>(nwx) * nwy, A(0));
+    const size_t n = static_cast<size_t>(nwx) * nwy;
+    std::vector<A> out(2 * n, A(0));
     const int width = L + R + 1;
     for (int q = 0; q <= T + B; ++q)
-        for (int p = 0; p <= L + R; ++p) out[q * nwx + p] = static_cast<A>(w[q * width + p]);
+        for (int p = 0; p <= L + R; ++p) {
+            out[q * nwx + p] = static_cast<A>(w[q * width + p]);
+            out[n + (T + B - q) * nwx + p] = static_cast<A>(w[q * width + p]);
+        }
     return out;
 }
 
@@ -372,6 +378,8 @@ mxs_status mxs_create_2d(const mxs_stencil2d_desc *d, mxs_plan *plan) {
         return hip_fail(e, "weights upload");
     }
     p->a.wts = p->wts.ptr;
+    p->a.wts_up = static_cast<const char *>(p->wts.ptr) +
+                  static_cast<size_t>(nwx) * nwy * (p->dtype == F64 ? sizeof(double) : sizeof(float));
     register_plan(p);
     *plan = p;
     return MXS_OK;

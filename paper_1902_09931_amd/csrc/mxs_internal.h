@@ -223,6 +223,7 @@ struct Stencil2DArgs {
     int periodic;
     int ncoe;
     const void *wts;        // device, NWY x NWX padded weights in the accumulation type
+    const void *wts_up;     // the same window flipped vertically (rows walked upward)
     double coe_d[kMaxCoe];
     float coe_f[kMaxCoe];
     int rows;               // output rows per workgroup

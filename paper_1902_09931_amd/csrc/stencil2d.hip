@@ -85,6 +85,15 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
     const int niter = H + NWY - 1;
     const long long ib = i0 + static_cast<long long>(t) * V;
     const bool periodic = a.periodic != 0;
+    // Odd chunks walk their rows bottom to top (the window flipped
+    // vertically), so the halo rows two neighbouring chunks share are read
+    // by both at about the same time and the second read hits in L2.
+    const bool up = (chunk & 1) != 0;
+    // first input row, and the step between input rows
+    const long long rfirst = up ? static_cast<long long>(j0) + H - 1 + a.B : static_cast<long long>(j0) - a.T;
+    const int rstep = up ? -1 : 1;
+    // upward chunks use the vertically flipped weights (uploaded by the plan)
+    const A *__restrict__ wv = up ? static_cast<const A *>(a.wts_up) : w;
     const bool full_vec = a.vec_ok && (ib + V <= a.nx);
     const bool store_vec_ok = full_vec && (periodic || (ib >= a.L && ib + V - 1 <= a.nx - 1 - a.R));
 
@@ -103,7 +112,7 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int s = s0 + u;
-            long long r = static_cast<long long>(j0) - a.T + s;
+            long long r = rfirst + static_cast<long long>(rstep) * s;
             bool rv = s < niter;
             if (periodic) r = wrap_ll(r, a.ny);
             else rv = rv && r >= 0 && r < a.ny;
@@ -130,7 +139,7 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
                     const int hh = h - u * 2 * PAD;
                     const long long c = hh < PAD ? i0 - PAD + hh : i0 + W + (hh - PAD);
                     const int s = s0 + u;
-                    long long r = static_cast<long long>(j0) - a.T + s;
+                    long long r = rfirst + static_cast<long long>(rstep) * s;
                     bool rv = s < niter;
                     if (periodic) r = wrap_ll(r, a.ny);
                     else rv = rv && r >= 0 && r < a.ny;
@@ -149,14 +158,14 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
         for (int k = 0; k < NWY; ++k) {
 #pragma unroll
             for (int p = 0; p < NWX; ++p) {
-                const A wt = w[(NWY - 1 - k) * NWX + p];
+                const A wt = wv[(NWY - 1 - k) * NWX + p];
 #pragma unroll
                 for (int v = 0; v < V; ++v) acc[k][v] = fma(wt, x[v + p], acc[k][v]);
             }
         }
         const int jj = s - (NWY - 1);
         if (jj >= 0 && jj < H) {
-            const int j = j0 + jj;
+            const int j = up ? j0 + H - 1 - jj : j0 + jj;
             if (periodic || (j >= a.T && j <= a.ny - 1 - a.B)) {
                 T *rowp = out + static_cast<long long>(j) * a.ld;
                 if (store_vec_ok) {
