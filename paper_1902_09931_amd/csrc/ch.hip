@@ -23,6 +23,13 @@ template <typename A> __device__ __forceinline__ A cd_of(const RhsInst &I);
 template <> __device__ __forceinline__ double cd_of<double>(const RhsInst &I) { return I.cdiff; }
 template <> __device__ __forceinline__ float cd_of<float>(const RhsInst &I) { return I.cdifff; }
 
+// Taps of the 13-point biharmonic (5x5) and 5-point Laplacian (3x3) windows;
+// the others are zero and are skipped at compile time.
+constexpr bool bih_tap(int q, int p) {
+    return q == 2 || p == 2 || ((q == 1 || q == 3) && (p == 1 || p == 3));
+}
+constexpr bool lap_tap(int q, int p) { return q == 1 || p == 1; }
+
 template <typename T, typename TW>
 __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__restrict__ inst,
                                                              const int *__restrict__ map) {
@@ -58,6 +65,17 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
     const gptr<const T> prev = as_global(static_cast<const T *>(I.prev));
     const gptr<TW> R = as_global(static_cast<TW *>(I.R));
     const A cdiff = cd_of<A>(I);
+    A wb[25], wl[9];
+#pragma unroll
+    for (int k = 0; k < 25; ++k) wb[k] = bih_tap(k / 5, k % 5) ? wb_of<A>(I, k) : A(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) wl[k] = lap_tap(k / 3, k % 3) ? wl_of<A>(I, k) : A(0);
+    // Odd chunks walk their rows upward (the windows are symmetric in y), so
+    // the halo rows two neighbouring chunks share are read by both at about
+    // the same time and the second read hits in L2.
+    const bool up = (chunk & 1) != 0;
+    const int rfirst = up ? j0 + H - 1 + 2 : j0 - 2;
+    const int rstep = up ? -1 : 1;
 
     A acc[5][V];
 #pragma unroll
@@ -73,7 +91,7 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
     auto load_stage = [&](int s0, A (&c)[G][V], A (&p)[G][V], A (&hc)[HPT], A (&hp)[HPT]) {
 #pragma unroll
         for (int u = 0; u < G; ++u) {
-            const int r = static_cast<int>(wrap_ll(j0 - 2 + s0 + u, ny));
+            const int r = static_cast<int>(wrap_fast(rfirst + rstep * (s0 + u), ny));
             const gptr<const T> cr = cur + static_cast<long long>(r) * nx;
             const gptr<const T> pr = prev + static_cast<long long>(r) * nx;
             if (full_vec) {
@@ -95,10 +113,10 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
             if (h < hcount) {
                 const int u = h / (2 * PAD);
                 const int hh = h - u * 2 * PAD;
-                const int r = static_cast<int>(wrap_ll(j0 - 2 + s0 + u, ny));
+                const int r = static_cast<int>(wrap_fast(rfirst + rstep * (s0 + u), ny));
                 const long long col = hh < PAD ? static_cast<long long>(i0) - PAD + hh
                                                : static_cast<long long>(i0) + W + (hh - PAD);
-                const long long o = static_cast<long long>(r) * nx + wrap_ll(col, nx);
+                const long long o = static_cast<long long>(r) * nx + wrap_fast(col, nx);
                 vc = to_acc<T>(gld<T>(cur, o));
                 vp = to_acc<T>(gld<T>(prev, o));
             }
@@ -152,8 +170,8 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
                 for (int k = 0; k < 5; ++k) {
 #pragma unroll
                     for (int p = 0; p < 5; ++p) {
-                        const A w = wb_of<A>(I, (4 - k) * 5 + p);
-                        if (w != A(0)) {
+                        if (bih_tap(4 - k, p)) {
+                            const A w = wb[(4 - k) * 5 + p];
 #pragma unroll
                             for (int v = 0; v < V; ++v) acc[k][v] = fma(w, x[v + p], acc[k][v]);
                         }
@@ -163,8 +181,8 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
                 for (int k = 1; k <= 3; ++k) {
 #pragma unroll
                     for (int p = 0; p < 3; ++p) {
-                        const A w = wl_of<A>(I, (3 - k) * 3 + p);
-                        if (w != A(0)) {
+                        if (lap_tap(3 - k, p)) {
+                            const A w = wl[(3 - k) * 3 + p];
 #pragma unroll
                             for (int v = 0; v < V; ++v) acc[k][v] = fma(w, y[v + p], acc[k][v]);
                         }
@@ -175,7 +193,7 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
 
                 const int jj = s - 4;
                 if (jj >= 0 && jj < H) {
-                    const gptr<TW> rowp = R + static_cast<long long>(j0 + jj) * nx;
+                    const gptr<TW> rowp = R + static_cast<long long>(up ? j0 + H - 1 - jj : j0 + jj) * nx;
                     if (full_vec) {
                         store_vec_nt<TW>(rowp + ib, acc[0]);
                     } else {

@@ -188,6 +188,14 @@ __device__ __forceinline__ long long wrap_ll(long long k, long long n) {
     long long r = k % n;
     return r < 0 ? r + n : r;
 }
+// k mod n with one conditional add or subtract for -n <= k < 2n (halo
+// indices); the division only for indices farther out.
+__device__ __forceinline__ long long wrap_fast(long long k, long long n) {
+    if (k < 0) k += n;
+    else if (k >= n) k -= n;
+    if (k < 0 || k >= n) k = wrap_ll(k, n);
+    return k;
+}
 
 // Point function f(c) = sum_m coe[m] c^m by Horner's rule; identity when
 // ncoe == 0.

@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
             const int s = s0 + u;
             long long r = rfirst + static_cast<long long>(rstep) * s;
             bool rv = s < niter;
-            if (periodic) r = wrap_ll(r, a.ny);
+            if (periodic) r = wrap_fast(r, a.ny);
             else rv = rv && r >= 0 && r < a.ny;
             if (rv) {
                 const T *rowp = in + r * a.ld;
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
                     const int s = s0 + u;
                     long long r = rfirst + static_cast<long long>(rstep) * s;
                     bool rv = s < niter;
-                    if (periodic) r = wrap_ll(r, a.ny);
+                    if (periodic) r = wrap_fast(r, a.ny);
                     else rv = rv && r >= 0 && r < a.ny;
                     if (rv) val = load_elem<T>(in + r * a.ld, c, a.nx, periodic);
                 }
