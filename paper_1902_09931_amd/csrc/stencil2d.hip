@@ -107,8 +107,55 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
     constexpr int HPT = (G * 2 * PAD + 63) / 64;
     const int hcount = G * 2 * PAD;
 
-    // Issue the loads of stage s0 (main vectors and halo values) into registers.
+    // A stage is "clean" when all its G rows exist (periodic, or inside the
+    // grid) and the strip lies inside the grid with aligned vectors: its
+    // loads are then issued as straight-line code with no alternative path
+    // writing the same registers, so none of them waits for the others (or
+    // for earlier stores); halo values outside a non-periodic grid are loaded
+    // from a clamped address and zeroed when staged.
+    const bool strip_clean = a.vec_ok && i0 + W <= a.nx;
+    auto clean_stage = [&](int s0) {
+        if (!strip_clean || s0 + G > niter) return false;
+        if (periodic) return true;
+        const long long ra = rfirst + static_cast<long long>(rstep) * s0;
+        const long long rb = rfirst + static_cast<long long>(rstep) * (s0 + G - 1);
+        return (ra < rb ? ra : rb) >= 0 && (ra > rb ? ra : rb) < a.ny;
+    };
+    // halo slot h of a stage: its row within the stage and its column
+    auto halo_slot = [&](int h, int &u, long long &c) {
+        u = h / (2 * PAD);
+        const int hh = h - u * 2 * PAD;
+        c = hh < PAD ? i0 - PAD + hh : i0 + W + (hh - PAD);
+    };
+
+    // Loads of a clean stage s0 (main vectors and halo values) into registers.
+    auto load_clean = [&](int s0, A (&xin)[G][V], A (&hv)[HPT > 0 ? HPT : 1]) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            long long r = rfirst + static_cast<long long>(rstep) * (s0 + u);
+            if (periodic) r = wrap_fast(r, a.ny);
+            load_vec<T>(in + r * a.ld + ib, xin[u]);
+        }
+        if constexpr (NWX > 1) {
+#pragma unroll
+            for (int q = 0; q < HPT; ++q) {
+                const int h = min(t + q * nt, hcount - 1);
+                int u;
+                long long c;
+                halo_slot(h, u, c);
+                c = periodic ? wrap_fast(c, a.nx) : (c < 0 ? 0 : (c >= a.nx ? a.nx - 1 : c));
+                long long r = rfirst + static_cast<long long>(rstep) * (s0 + u);
+                if (periodic) r = wrap_fast(r, a.ny);
+                hv[q] = to_acc<T>(in[r * a.ld + c]);
+            }
+        }
+    };
+    // Loads of any stage s0.
     auto load_stage = [&](int s0, A (&xin)[G][V], A (&hv)[HPT > 0 ? HPT : 1]) {
+        if (clean_stage(s0)) {
+            load_clean(s0, xin, hv);
+            return;
+        }
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int s = s0 + u;
@@ -153,7 +200,8 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
     // acc[k] holds output row s - (NWY-1) + k; input row s meets it with
     // window row NWY-1-k.  After the row, acc[0] is complete: it is written
     // and the window shifts by one row.
-    auto consume = [&](const A *x, int s) {
+    // clean: the output row exists and the whole strip is stored with vectors
+    auto consume = [&](const A *x, int s, bool clean) {
 #pragma unroll
         for (int k = 0; k < NWY; ++k) {
 #pragma unroll
@@ -164,7 +212,11 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
             }
         }
         const int jj = s - (NWY - 1);
-        if (jj >= 0 && jj < H) {
+        if (clean) {
+            T *rowp = out + static_cast<long long>(up ? j0 + H - 1 - jj : j0 + jj) * a.ld;
+            if (a.nt_store) store_vec_nt<T>(rowp + ib, acc[0]);
+            else store_vec<T>(rowp + ib, acc[0]);
+        } else if (jj >= 0 && jj < H) {
             const int j = up ? j0 + H - 1 - jj : j0 + jj;
             if (periodic || (j >= a.T && j <= a.ny - 1 - a.B)) {
                 T *rowp = out + static_cast<long long>(j) * a.ld;
@@ -189,11 +241,26 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
         for (int v = 0; v < V; ++v) acc[NWY - 1][v] = A(0);
     };
 
+    // A stage is consumed "clean" when its G rows all produce output rows that
+    // exist, the strip is stored with whole vectors, and the next stage's
+    // loads are clean too: its loads and stores are then straight-line code
+    // with fixed counts, so waiting for the next stage's loads never waits
+    // for this stage's stores.
+    const bool strip_store_clean =
+        strip_clean && (periodic || (i0 >= a.L && i0 + W - 1 <= static_cast<long long>(a.nx) - 1 - a.R));
+    auto clean_iter = [&](int s0) {
+        if (!strip_store_clean || s0 < NWY - 1 || s0 + G - NWY >= H || !clean_stage(s0 + G)) return false;
+        if (periodic) return true;
+        const int ja = up ? j0 + H - 1 - (s0 - (NWY - 1)) : j0 + (s0 - (NWY - 1));
+        const int jb = up ? j0 + H - 1 - (s0 + G - NWY) : j0 + (s0 + G - NWY);
+        return (ja < jb ? ja : jb) >= a.T && (ja > jb ? ja : jb) <= a.ny - 1 - a.B;
+    };
+
     A cur[G][V], nxt[G][V];
     A hcur[HPT > 0 ? HPT : 1], hnxt[HPT > 0 ? HPT : 1];
     load_stage(0, cur, hcur);
 
-    for (int s0 = 0; s0 < niter; s0 += G) {
+    auto iteration = [&](int s0, bool clean) {
         // the point function is applied once per loaded element
         if (a.ncoe) {
 #pragma unroll
@@ -213,33 +280,39 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
 #pragma unroll
                 for (int v = 0; v < V; ++v) dst[v] = cur[u][v];
             }
+            const bool cl = clean_stage(s0);
 #pragma unroll
             for (int q = 0; q < HPT; ++q) {
                 const int h = t + q * nt;
                 if (h < hcount) {
                     const int u = h / (2 * PAD);
                     const int hh = h - u * 2 * PAD;
-                    lds[u * rowlen + (hh < PAD ? hh : W + hh)] = hcur[q];
+                    long long c;
+                    int uu;
+                    halo_slot(h, uu, c);
+                    const bool zero = cl && !periodic && (c < 0 || c >= a.nx);
+                    lds[u * rowlen + (hh < PAD ? hh : W + hh)] = zero ? A(0) : hcur[q];
                 }
             }
         }
         // next stage's loads overlap this stage's arithmetic
-        if (s0 + G < niter) load_stage(s0 + G, nxt, hnxt);
+        if (clean) load_clean(s0 + G, nxt, hnxt);
+        else if (s0 + G < niter) load_stage(s0 + G, nxt, hnxt);
         if constexpr (NWX > 1) {
             __syncthreads();
-            const int nu = min(G, niter - s0);
+            const int nu = clean ? G : min(G, niter - s0);
 #pragma unroll 1
             for (int u = 0; u < nu; ++u) {
                 A x[XW];
                 const A *lp = lds + u * rowlen + PAD + t * V - a.L;
 #pragma unroll
                 for (int k = 0; k < XW; ++k) x[k] = lp[k];
-                consume(x, s0 + u);
+                consume(x, s0 + u, clean);
             }
         } else {
 #pragma unroll
             for (int u = 0; u < G; ++u)
-                if (s0 + u < niter) consume(cur[u], s0 + u);
+                if (clean || s0 + u < niter) consume(cur[u], s0 + u, clean);
         }
 #pragma unroll
         for (int u = 0; u < G; ++u)
@@ -247,6 +320,20 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
             for (int v = 0; v < V; ++v) cur[u][v] = nxt[u][v];
 #pragma unroll
         for (int q = 0; q < (HPT > 0 ? HPT : 1); ++q) hcur[q] = hnxt[q];
+    };
+
+    int s0 = 0;
+    while (s0 < niter && !clean_iter(s0)) {
+        iteration(s0, false);
+        s0 += G;
+    }
+    while (s0 < niter && clean_iter(s0)) {
+        iteration(s0, true);
+        s0 += G;
+    }
+    while (s0 < niter) {
+        iteration(s0, false);
+        s0 += G;
     }
 }
 
