@@ -261,16 +261,34 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
     load_stage(0, cur, hcur);
 
     auto iteration = [&](int s0, bool clean) {
-        // the point function is applied once per loaded element
+        // the point function is applied once per loaded element: Horner's
+        // rule with the coefficient loop outside and the stage's elements
+        // inside (the same operations, in the same order, per element)
         if (a.ncoe) {
+            constexpr int HQ = NWX > 1 ? HPT : 0;
+            A f[G][V], hf[HQ > 0 ? HQ : 1];
+            const A top = coe[a.ncoe - 1];
 #pragma unroll
             for (int u = 0; u < G; ++u)
 #pragma unroll
-                for (int v = 0; v < V; ++v) cur[u][v] = point_fun<A>(cur[u][v], coe, a.ncoe);
-            if constexpr (NWX > 1) {
+                for (int v = 0; v < V; ++v) f[u][v] = top;
 #pragma unroll
-                for (int q = 0; q < HPT; ++q) hcur[q] = point_fun<A>(hcur[q], coe, a.ncoe);
+            for (int q = 0; q < HQ; ++q) hf[q] = top;
+            for (int m = a.ncoe - 2; m >= 0; --m) {
+                const A cm = coe[m];
+#pragma unroll
+                for (int u = 0; u < G; ++u)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) f[u][v] = f[u][v] * cur[u][v] + cm;
+#pragma unroll
+                for (int q = 0; q < HQ; ++q) hf[q] = hf[q] * hcur[q] + cm;
             }
+#pragma unroll
+            for (int u = 0; u < G; ++u)
+#pragma unroll
+                for (int v = 0; v < V; ++v) cur[u][v] = f[u][v];
+#pragma unroll
+            for (int q = 0; q < HQ; ++q) hcur[q] = hf[q];
         }
         if constexpr (NWX > 1) {
             __syncthreads();   // the previous stage's LDS reads are done
