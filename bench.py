@@ -355,6 +355,39 @@ def cpu_baseline(wl, n, rows):
                       f"{os.cpu_count()} host cores visible)"}
 
 
+def cpu_baseline_threads(wl, n, rows):
+    """The same oracle calls spread over the host cores: each thread runs the
+    eight stencils on its own band of rows of the slice (independent calls of
+    the unchanged oracle, which releases the GIL inside its C code)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    nthreads = max(1, min(len(os.sched_getaffinity(0)), 16))
+    band = (rows + nthreads - 1) // nthreads
+    u = wl.uniform_grid(rows, n, seed=1)
+    bands = [np_ascontig(u[k:k + band]) for k in range(0, rows, band)]
+    dx = 1.0 / n
+
+    def work(ub):
+        for name, d, ext, w, coe in stencil_set(wl, dx):
+            for periodic in (True, False):
+                oracle.stencil2d(ub, *ext, w, periodic, coe=coe)
+
+    with ThreadPoolExecutor(len(bands)) as pool:
+        t0 = time.perf_counter()
+        list(pool.map(work, bands))
+        sec = time.perf_counter() - t0
+    pts = 8 * rows * n
+    return {"value": pts / sec / 1e9, "unit": "Gpoints/s", "cores": len(bands), "kind": "oracle",
+            "sample": f"the eight stencils of one step on a {rows} x {n} slice split into "
+                      f"{len(bands)} bands of rows, one thread each ({pts} point updates, "
+                      f"{sec:.2f} s)"}
+
+
+def np_ascontig(a):
+    import numpy as np
+    return np.ascontiguousarray(a)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -460,6 +493,7 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(wl, n, rows=min(n, 3072))
+        extra["cpu_baseline_all_cores"] = cpu_baseline_threads(wl, n, rows=min(n, 3072))
     if args.sections_only:     # no headline was measured: report the sections alone
         result = {"sections_only": True, "extra": extra}
     print(json.dumps(result), flush=True)
