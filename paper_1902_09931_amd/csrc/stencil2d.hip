@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
     // for earlier stores); halo values outside a non-periodic grid are loaded
     // from a clamped address and zeroed when staged.
     const bool strip_clean = a.vec_ok && i0 + W <= a.nx;
-    auto clean_stage = [&](int s0) {
+    auto clean_stage = [&](int s0) __attribute__((always_inline)) {
         if (!strip_clean || s0 + G > niter) return false;
         if (periodic) return true;
         const long long ra = rfirst + static_cast<long long>(rstep) * s0;
@@ -122,14 +122,14 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
         return (ra < rb ? ra : rb) >= 0 && (ra > rb ? ra : rb) < a.ny;
     };
     // halo slot h of a stage: its row within the stage and its column
-    auto halo_slot = [&](int h, int &u, long long &c) {
+    auto halo_slot = [&](int h, int &u, long long &c) __attribute__((always_inline)) {
         u = h / (2 * PAD);
         const int hh = h - u * 2 * PAD;
         c = hh < PAD ? i0 - PAD + hh : i0 + W + (hh - PAD);
     };
 
     // Loads of a clean stage s0 (main vectors and halo values) into registers.
-    auto load_clean = [&](int s0, A (&xin)[G][V], A (&hv)[HPT > 0 ? HPT : 1]) {
+    auto load_clean = [&](int s0, A (&xin)[G][V], A (&hv)[HPT > 0 ? HPT : 1]) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             long long r = rfirst + static_cast<long long>(rstep) * (s0 + u);
@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
         }
     };
     // Loads of any stage s0.
-    auto load_stage = [&](int s0, A (&xin)[G][V], A (&hv)[HPT > 0 ? HPT : 1]) {
+    auto load_stage = [&](int s0, A (&xin)[G][V], A (&hv)[HPT > 0 ? HPT : 1]) __attribute__((always_inline)) {
         if (clean_stage(s0)) {
             load_clean(s0, xin, hv);
             return;
@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
     // window row NWY-1-k.  After the row, acc[0] is complete: it is written
     // and the window shifts by one row.
     // clean: the output row exists and the whole strip is stored with vectors
-    auto consume = [&](const A *x, int s, bool clean) {
+    auto consume = [&](const A *x, int s, bool clean) __attribute__((always_inline)) {
 #pragma unroll
         for (int k = 0; k < NWY; ++k) {
 #pragma unroll
@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
     // for this stage's stores.
     const bool strip_store_clean =
         strip_clean && (periodic || (i0 >= a.L && i0 + W - 1 <= static_cast<long long>(a.nx) - 1 - a.R));
-    auto clean_iter = [&](int s0) {
+    auto clean_iter = [&](int s0) __attribute__((always_inline)) {
         if (!strip_store_clean || s0 < NWY - 1 || s0 + G - NWY >= H || !clean_stage(s0 + G)) return false;
         if (periodic) return true;
         const int ja = up ? j0 + H - 1 - (s0 - (NWY - 1)) : j0 + (s0 - (NWY - 1));
@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
     A hcur[HPT > 0 ? HPT : 1], hnxt[HPT > 0 ? HPT : 1];
     load_stage(0, cur, hcur);
 
-    auto iteration = [&](int s0, bool clean) {
+    auto iteration = [&](int s0, bool clean) __attribute__((always_inline)) {
         // the point function is applied once per loaded element: Horner's
         // rule with the coefficient loop outside and the stage's elements
         // inside (the same operations, in the same order, per element)
