@@ -44,9 +44,9 @@ inline size_t line_lds_bytes(long long nmax, int nw) {
 }
 
 // --- lines held in the registers of one wavefront -----------------------------
-// A line of at most kWaveLineMax elements is held by one wavefront: blocks of
-// kWaveBlock elements, 4 consecutive elements per lane.  Each block is
-// scanned across the lanes with powers of the companion matrix
+// A line of at most kWaveLineMax elements is held by one wavefront, E = 4, 8
+// or 16 consecutive elements per lane in blocks of 64 E (by length class).
+// The lane states are scanned with powers of the companion matrix
 // M = [[p1, p2], [1, 0]] taken from a table: entries k = 0..kWaveBlock hold
 // M^k, entries kWaveBlock + 1 + c hold M^(kWaveBlock c), c = 0..kWaveNBMax;
 // each entry is 4 doubles, row-major.
@@ -55,10 +55,11 @@ constexpr int kWaveNBMax = 16;
 constexpr int kWaveLineMax = kWaveBlock * kWaveNBMax;
 constexpr int kPowEntries = kWaveBlock + 1 + kWaveNBMax + 1;
 void fill_pow_table(const CyclicFactor &f, int bw, double *out);   // 4 * kPowEntries doubles
-// Register blocks of the kernel that holds a line of n elements (n <= kWaveLineMax).
+// Length class of a line of n elements (n <= kWaveLineMax): the number of
+// kWaveBlock-element blocks it may span, 1, 2, 4, 8 or 16.
 inline int wave_nb(long long n) {
     const long long nb = (n + kWaveBlock - 1) / kWaveBlock;
-    return nb <= 2 ? 2 : nb <= 4 ? 4 : nb <= 8 ? 8 : 16;
+    return nb <= 1 ? 1 : nb <= 2 ? 2 : nb <= 4 ? 4 : nb <= 8 ? 8 : 16;
 }
 // The LDS kernel is used for every line when MXS_LINE_KERNEL=lds (tests).
 inline bool force_lds_lines() {

@@ -5,27 +5,30 @@
 // cyclic, then x = u / K (the periodic line inversions of the ADI scheme,
 // Sec. 5.1).
 //
-// Layout: block c of the line holds elements 256 c .. 256 c + 255; lane l
-// holds the four consecutive elements 256 c + 4 l + j, j = 0..3, of every
-// block, so no shared memory is needed.  With the state s_i = (y_i, y_{i-1})
-// the recurrence is s_i = M s_{i-1} + (r_i, 0), M = [[p1, p2], [1, 0]], and
-// a value is its local value from a zero state plus row 0 of M^{k+1} times
-// the state k + 1 steps before it.
+// Layout: the line is cut into blocks of 64 E elements; in every block lane l
+// holds the E consecutive elements 64 E c + E l + j, j = 0..E-1 (E = 4, 8 or
+// 16 by line length).  Loads and stores stay coalesced: a block is read with
+// one element per lane per instruction and transposed through a small LDS
+// buffer of the wavefront.  With the state s_i = (y_i, y_{i-1}) the
+// recurrence is s_i = M s_{i-1} + (r_i, 0), M = [[p1, p2], [1, 0]].
 //
-// Forward recurrence:
-//   1. block by block, from zero at the line start: each lane runs the
-//      recurrence over its four elements from zero; an inclusive scan within
-//      each row of 16 lanes (DPP row shifts, multipliers M^4, M^8, M^16,
-//      M^32) and a chain over the four row totals (read with readlane,
-//      multiplier M^64) starting from the state entering the block give
-//      every lane its incoming state, hence every value, and the state after
-//      the block;
-//   2. the cyclic closure: with F the state after the last element, the true
-//      state entering the line is x0 = (I - M^n)^{-1} F, and value i gains
-//      row 0 of M^{i+1} x0 (M^{i+1} = M^{j+1} M^{4p} M^{64 row} M^{256 c}).
+// Each direction takes two passes over the registers:
+//   A. from a zero state at the line start: every lane runs the recurrence
+//      over its E elements; a scan of the lane totals within each row of 16
+//      lanes (DPP row shifts, multipliers M^E .. M^8E) and a chain over the
+//      four row totals (readlane, multiplier M^16E) from the state entering
+//      the block give every lane the state entering it, and the state after
+//      the line's last element, F;
+//   B. the cyclic closure x0 = (I - M^n)^{-1} F is the true state entering
+//      the line; a lane's true incoming state is its zero-start state plus
+//      M^(index of its first element) x0, and the lane reruns its recurrence
+//      from it, which gives the true values directly.
 // The backward recurrence is the same with the order of blocks, rows, lanes
-// and elements reversed, its closure term row 0 of M^{n-i} z0.  All powers of
-// M come from a table computed on the host.
+// and elements reversed (closure z0 from the state after element 0), and its
+// values leave scaled by 1/K.  Elements past the line's end are zero inputs;
+// from a zero state they keep the state zero, so the top of a partial block
+// needs no special case in the backward zero-start pass.  All powers of M
+// come from a table computed on the host: M^k (k <= 256) and M^(256 c).
 #include "lines_dev.h"
 
 namespace mxs {
@@ -58,15 +61,15 @@ template <int BW> __device__ __forceinline__ S2 mv(const Mat &m, S2 u) {
     if constexpr (BW == 2) return S2{fma(m.a, u.x, m.b * u.y), fma(m.c, u.x, m.d * u.y)};
     else return S2{m.a * u.x, 0.0};
 }
-// row 0 of m times u
-template <int BW> __device__ __forceinline__ double row0(const Mat &m, S2 u) {
-    if constexpr (BW == 2) return fma(m.a, u.x, m.b * u.y);
-    else return m.a * u.x;
-}
 
 __device__ __forceinline__ Mat mat_mul(const Mat &x, const Mat &y) {
     return Mat{fma(x.a, y.a, x.b * y.c), fma(x.a, y.b, x.b * y.d), fma(x.c, y.a, x.d * y.c),
                fma(x.c, y.b, x.d * y.d)};
+}
+
+// M^k for 0 <= k <= 16 * 256, from the table (pw: M^k, k <= 256; pb: M^(256 c))
+__device__ __forceinline__ Mat pow_mat(gptr<const double> pw, gptr<const double> pb, int k) {
+    return mat_mul(load_mat(pw + 4 * (k & (kWaveBlock - 1))), load_mat(pb + 4 * (k / kWaveBlock)));
 }
 
 // (I - m)^{-1} f
@@ -95,6 +98,7 @@ template <int CTRL, int BW> __device__ __forceinline__ S2 dpp_s(S2 v) {
     return S2{dpp_d<CTRL>(v.x), BW == 2 ? dpp_d<CTRL>(v.y) : 0.0};
 }
 
+// value of lane `lane` (uniform) of a double
 __device__ __forceinline__ double readlane_d(double v, int lane) {
     const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
     const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b), lane));
@@ -105,208 +109,241 @@ template <int BW> __device__ __forceinline__ S2 readlane_s(S2 v, int lane) {
     return S2{readlane_d(v.x, lane), BW == 2 ? readlane_d(v.y, lane) : 0.0};
 }
 
-template <int BW> __device__ __forceinline__ S2 pick_row(int r, S2 a0, S2 a1, S2 a2, S2 a3) {
-    const S2 lo = r == 0 ? a0 : a1, hi = r == 2 ? a2 : a3;
-    return r < 2 ? lo : hi;
+// cond ? a : b, per component (a select of the whole struct goes through
+// the stack)
+template <int BW> __device__ __forceinline__ S2 keep_if(bool cond, S2 a, S2 b) {
+    return S2{cond ? a.x : b.x, BW == 2 ? (cond ? a.y : b.y) : 0.0};
 }
 
-// Uniform powers of M used by every block.
-struct Powers {
-    Mat m4[4];          // M^4, M^8, M^16, M^32 (row scan steps)
-    Mat m64;            // row carries
-    Mat e[5];           // M^1 .. M^4 (element factors; e[0] unused)
+template <int BW> __device__ __forceinline__ S2 pick_row(int r, S2 a0, S2 a1, S2 a2, S2 a3) {
+    return keep_if<BW>(r < 2, keep_if<BW>(r == 0, a0, a1), keep_if<BW>(r == 2, a2, a3));
+}
+
+// Orders the LDS accesses of one wavefront around a lane exchange: the
+// hardware executes a wavefront's LDS instructions in order, the fences keep
+// the compiler from moving them.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Register layout of a length class (nb = blocks of 256 the line may span):
+// E elements per lane, NBB blocks of 64 E elements.
+template <int NB> struct WaveShape;
+template <> struct WaveShape<1> { static constexpr int E = 4, NBB = 1; };
+template <> struct WaveShape<2> { static constexpr int E = 8, NBB = 1; };
+template <> struct WaveShape<4> { static constexpr int E = 16, NBB = 1; };
+template <> struct WaveShape<8> { static constexpr int E = 16, NBB = 2; };
+template <> struct WaveShape<16> { static constexpr int E = 16, NBB = 4; };
+
+// LDS of one wavefront: one block, each lane's E elements followed by 16
+// bytes of padding, so that the chunk reads of consecutive lanes fall in
+// different banks.
+template <typename T, int E> struct Stage {
+    static constexpr int CH = E + 16 / static_cast<int>(sizeof(T));
+    static constexpr int SIZE = 64 * CH;
 };
 
-// Forward recurrence over one block, given fin, the state entering the block
-// (from zero at the line start): r[j] inputs (zero where invalid); v[j]
-// receive the values and the state after the block is returned (for a full
-// block).  Within a row of 16 lanes the lane states are scanned with DPP row
-// shifts; the four row totals are chained from fin.
-template <int BW>
-__device__ __forceinline__ S2 block_forward(const double (&r)[4], double (&v)[4], const Powers &P,
-                                            const Mat &Mp, int row, S2 fin, double p1, double p2) {
-    S2 s{0.0, 0.0};
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        s = rec<BW>(s, r[j], p1, p2);
-        v[j] = s.x;
-    }
-    s = mv_add<BW>(P.m4[0], dpp_s<0x111, BW>(s), s);
-    s = mv_add<BW>(P.m4[1], dpp_s<0x112, BW>(s), s);
-    s = mv_add<BW>(P.m4[2], dpp_s<0x114, BW>(s), s);
-    s = mv_add<BW>(P.m4[3], dpp_s<0x118, BW>(s), s);
-    const S2 ex = dpp_s<0x111, BW>(s);
-    const S2 c0 = fin;
-    const S2 c1 = mv_add<BW>(P.m64, c0, readlane_s<BW>(s, 15));
-    const S2 c2 = mv_add<BW>(P.m64, c1, readlane_s<BW>(s, 31));
-    const S2 c3 = mv_add<BW>(P.m64, c2, readlane_s<BW>(s, 47));
-    const S2 in = mv_add<BW>(Mp, pick_row<BW>(row, c0, c1, c2, c3), ex);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] += row0<BW>(P.e[j + 1], in);
-    return mv_add<BW>(P.m64, c3, readlane_s<BW>(s, 63));
-}
-
-// The same for the backward recurrence (elements, lanes and rows in
-// decreasing order); gin is the state entering the block's top element and
-// the state after its first element is returned.
-template <int BW>
-__device__ __forceinline__ S2 block_backward(const double (&r)[4], double (&v)[4], const Powers &P,
-                                             const Mat &Mq, int row, S2 gin, double p1, double p2) {
-    S2 s{0.0, 0.0};
-#pragma unroll
-    for (int j = 3; j >= 0; --j) {
-        s = rec<BW>(s, r[j], p1, p2);
-        v[j] = s.x;
-    }
-    s = mv_add<BW>(P.m4[0], dpp_s<0x101, BW>(s), s);
-    s = mv_add<BW>(P.m4[1], dpp_s<0x102, BW>(s), s);
-    s = mv_add<BW>(P.m4[2], dpp_s<0x104, BW>(s), s);
-    s = mv_add<BW>(P.m4[3], dpp_s<0x108, BW>(s), s);
-    const S2 ex = dpp_s<0x101, BW>(s);
-    const S2 c3 = gin;
-    const S2 c2 = mv_add<BW>(P.m64, c3, readlane_s<BW>(s, 48));
-    const S2 c1 = mv_add<BW>(P.m64, c2, readlane_s<BW>(s, 32));
-    const S2 c0 = mv_add<BW>(P.m64, c1, readlane_s<BW>(s, 16));
-    const S2 in = mv_add<BW>(Mq, pick_row<BW>(row, c0, c1, c2, c3), ex);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] += row0<BW>(P.e[4 - j], in);
-    return mv_add<BW>(P.m64, c0, readlane_s<BW>(s, 0));
-}
-
-// M^(64 r) u for the row r of the calling lane (m[k] = M^(64 k)).
-template <int BW> __device__ __forceinline__ S2 by_row(int row, const Mat (&m)[4], S2 u) {
-    return pick_row<BW>(row, u, mv<BW>(m[1], u), mv<BW>(m[2], u), mv<BW>(m[3], u));
-}
-
-// Solve line li with the wavefront of the calling lanes (all 64 active).
-template <typename TI, typename TO, int BW, int NB, class Src>
-__device__ __forceinline__ void wave_line(const Src &src, int li) {
-    constexpr int B = kWaveBlock;
+// Solve line li with the wavefront of the calling lanes (all 64 active);
+// buf is the wavefront's LDS stage.
+template <typename T, int BW, int NB, class Src>
+__device__ __forceinline__ void wave_line(const Src &src, int li, T *buf) {
+    constexpr int E = WaveShape<NB>::E, NBB = WaveShape<NB>::NBB;
+    constexpr int BLK = 64 * E;
+    constexpr int CH = Stage<T, E>::CH;
+    constexpr int LPC = 64 / E;   // lane chunks per 64 consecutive elements
     const int lane = threadIdx.x & 63;
     const int row = lane >> 4, p = lane & 15;
     const LineRef L = src.get(li);
     const int n = L.n;
-    const gptr<const double> pw = as_global(L.pow);   // M^k at pw + 4 k, k <= B
-    const gptr<const double> pb = pw + 4 * (B + 1);   // M^(B c) at pb + 4 c
+    const gptr<const double> pw = as_global(L.pow);
+    const gptr<const double> pb = pw + 4 * (kWaveBlock + 1);
     const double p1 = L.p1, p2 = L.p2;
-    const int nblk = (n + B - 1) / B;
-    const int last = nblk - 1;
-    const int len_last = n - B * last;
+    const int last = (n - 1) / BLK;
 
-    // every element of the line requested before any is used
-    const gptr<const TI> in = as_global(static_cast<const TI *>(L.in));
-    TI raw[4 * NB];
-    // (per-lane 32-bit offsets from the uniform line base; only the last
-    // block is clamped into the line)
-    const unsigned lo = 4u * lane;
+    // every element of the line requested before any is used: element
+    // BLK c + 64 k + lane by lane `lane` (coalesced), clamped into the line
+    // in the last block
+    const gptr<const T> in = as_global(static_cast<const T *>(L.in));
+    T raw[NBB][E];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
+    for (int c = 0; c < NBB; ++c) {
         if (c < last) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) raw[4 * c + j] = gld<TI>(in, lo + static_cast<unsigned>(B * c + j));
+            for (int k = 0; k < E; ++k) raw[c][k] = gld<T>(in, static_cast<unsigned>(BLK * c + 64 * k + lane));
         } else if (c == last) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                raw[4 * c + j] = gld<TI>(in, min(static_cast<int>(lo) + B * c + j, n - 1));
+            for (int k = 0; k < E; ++k) raw[c][k] = gld<T>(in, min(BLK * c + 64 * k + lane, n - 1));
         }
     }
-    Powers P;
-    P.m4[0] = load_mat(pw + 16);
-    P.m4[1] = load_mat(pw + 32);
-    P.m4[2] = load_mat(pw + 64);
-    P.m4[3] = load_mat(pw + 128);
-    P.m64 = load_mat(pw + 4 * 64);
-#pragma unroll
-    for (int k = 1; k <= 4; ++k) P.e[k] = load_mat(pw + 4 * k);
-    const Mat m64r[4] = {Mat{1.0, 0.0, 0.0, 1.0}, P.m64, load_mat(pw + 4 * 128), load_mat(pw + 4 * 192)};
-    const Mat Mp = load_mat(pw + 16 * p);          // M^(4 p)
-    const Mat Mq = load_mat(pw + 16 * (15 - p));   // M^(4 (15 - p))
-    const Mat Mlen = load_mat(pw + 4 * len_last);
-    const Mat Mn = mat_mul(Mlen, load_mat(pb + 4 * last));   // M^n
+    // element 64 k + lane of a block sits in chunk LPC k + lane / E, slot lane % E
+    const int wslot = (lane / E) * CH + lane % E;
 
-    // forward recurrence from zero at the line start
-    double y[4 * NB];
+    Mat K[4];   // M^E, M^2E, M^4E, M^8E: the row scan steps
+#pragma unroll
+    for (int i = 0; i < 4; ++i) K[i] = load_mat(pw + 4 * (E << i));
+    const Mat Mrow = load_mat(pw + 4 * (16 * E));   // M^16E: one row of lanes
+    const Mat Mn = pow_mat(pw, pb, n);
+
+    double v[NBB][E];
+    // valid elements of the calling lane in the last block
+    const int cnt = min(max(n - BLK * last - E * lane, 0), E);
+
+    // forward pass A: zero-start state entering every lane, and F
+    S2 in0[NBB];
     S2 F{0.0, 0.0};
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-        if (c < last) {
-            double r[4], v[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) r[j] = to_f64<TI>(raw[4 * c + j]);
-            F = block_forward<BW>(r, v, P, Mp, row, F, p1, p2);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) y[4 * c + j] = v[j];
-        } else if (c == last) {
-            const int i0 = B * c + 4 * lane;
-            double r[4], v[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) r[j] = i0 + j < n ? to_f64<TI>(raw[4 * c + j]) : 0.0;
-            (void)block_forward<BW>(r, v, P, Mp, row, F, p1, p2);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) y[4 * c + j] = v[j];
-        }
-    }
-    // state after element n - 1, read from the values of the last block
-    // (element n - 2 may be the last one of the block before)
-    S2 Fl{0.0, 0.0};
     {
-        const int jl = len_last - 1, jm = len_last - 2;
+        const Mat Mp = load_mat(pw + 4 * (E * p));   // M^(E p)
+        S2 C{0.0, 0.0};                              // zero-start state entering block c
 #pragma unroll
-        for (int c = 0; c < NB; ++c) {
-            if (c == last) {
+        for (int c = 0; c < NBB; ++c) {
+            if (c <= last) {
+                // the block into the lanes' registers (through the LDS
+                // stage), while the later blocks' loads are still in flight
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if ((jl & 3) == j) Fl.x = readlane_d(y[4 * c + j], jl >> 2);
-                    if (BW == 2 && jm >= 0 && (jm & 3) == j) Fl.y = readlane_d(y[4 * c + j], jm >> 2);
+                for (int k = 0; k < E; ++k) buf[LPC * k * CH + wslot] = raw[c][k];
+                wave_sync();
+#pragma unroll
+                for (int j = 0; j < E; ++j) v[c][j] = to_f64<T>(buf[lane * CH + j]);
+                wave_sync();
+                S2 s{0.0, 0.0};
+                if (c < last) {
+#pragma unroll
+                    for (int j = 0; j < E; ++j) s = rec<BW>(s, v[c][j], p1, p2);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < E; ++j) {
+                        if (j >= cnt) v[c][j] = 0.0;
+                        const S2 t = rec<BW>(s, v[c][j], p1, p2);
+                        s = keep_if<BW>(j < cnt, t, s);
+                    }
                 }
-                if (BW == 2 && jm < 0 && c > 0) Fl.y = readlane_d(y[4 * c - 1], 63);
+                const S2 tot = s;
+                s = mv_add<BW>(K[0], dpp_s<0x111, BW>(s), s);
+                s = mv_add<BW>(K[1], dpp_s<0x112, BW>(s), s);
+                s = mv_add<BW>(K[2], dpp_s<0x114, BW>(s), s);
+                s = mv_add<BW>(K[3], dpp_s<0x118, BW>(s), s);
+                const S2 c0 = C;
+                const S2 c1 = mv_add<BW>(Mrow, c0, readlane_s<BW>(s, 15));
+                const S2 c2 = mv_add<BW>(Mrow, c1, readlane_s<BW>(s, 31));
+                const S2 c3 = mv_add<BW>(Mrow, c2, readlane_s<BW>(s, 47));
+                in0[c] = mv_add<BW>(Mp, pick_row<BW>(row, c0, c1, c2, c3), dpp_s<0x111, BW>(s));
+                if (c < last) {
+                    C = mv_add<BW>(Mrow, c3, readlane_s<BW>(s, 63));
+                } else {
+                    // state after element n - 1: its lane's incoming state
+                    // carried over the lane's valid elements
+                    const int ll = (n - 1 - BLK * c) / E;
+                    const int cl = n - BLK * c - E * ll;
+                    F = mv_add<BW>(load_mat(pw + 4 * cl), readlane_s<BW>(in0[c], ll), readlane_s<BW>(tot, ll));
+                }
             }
         }
     }
-    const S2 x0 = closure<BW>(Mn, Fl);
+    const S2 x0 = closure<BW>(Mn, F);
 
-    // true forward values (+ row 0 of M^(i+1) x0), then the backward
-    // recurrence from zero at the top, top block first
-    S2 G{0.0, 0.0};
+    // forward pass B: true values from the true incoming states
+    {
+        const Mat W = pow_mat(pw, pb, E * lane);   // M^(E lane)
 #pragma unroll
-    for (int c = NB - 1; c >= 0; --c) {
-        if (c <= last) {
-            const S2 w = mv<BW>(Mp, by_row<BW>(row, m64r, mv<BW>(load_mat(pb + 4 * c), x0)));
-            double r[4], v[4];
-            if (c == last) {
-                const int i0 = B * c + 4 * lane;
+        for (int c = 0; c < NBB; ++c) {
+            if (c <= last) {
+                const S2 xc = mv<BW>(load_mat(pb + 4 * ((BLK / kWaveBlock) * c)), x0);   // M^(BLK c) x0
+                S2 s = mv_add<BW>(W, xc, in0[c]);
+                if (c < last) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) r[j] = i0 + j < n ? y[4 * c + j] + row0<BW>(P.e[j + 1], w) : 0.0;
-            } else {
+                    for (int j = 0; j < E; ++j) {
+                        s = rec<BW>(s, v[c][j], p1, p2);
+                        v[c][j] = s.x;
+                    }
+                } else {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) r[j] = y[4 * c + j] + row0<BW>(P.e[j + 1], w);
+                    for (int j = 0; j < E; ++j) {
+                        s = rec<BW>(s, v[c][j], p1, p2);
+                        v[c][j] = j < cnt ? s.x : 0.0;
+                    }
+                }
             }
-            G = block_backward<BW>(r, v, P, Mq, row, G, p1, p2);
+        }
+    }
+
+    // backward pass A: zero-start state entering every lane from above, and
+    // the state after element 0 (the elements past the line's end are zero
+    // and keep the zero start state zero)
+    S2 in1[NBB];
+    S2 G{0.0, 0.0};
+    {
+        const Mat Mq = load_mat(pw + 4 * (E * (15 - p)));   // M^(E (15 - p))
 #pragma unroll
-            for (int j = 0; j < 4; ++j) y[4 * c + j] = v[j];
+        for (int c = NBB - 1; c >= 0; --c) {
+            if (c <= last) {
+                S2 s{0.0, 0.0};
+#pragma unroll
+                for (int j = E - 1; j >= 0; --j) s = rec<BW>(s, v[c][j], p1, p2);
+                s = mv_add<BW>(K[0], dpp_s<0x101, BW>(s), s);
+                s = mv_add<BW>(K[1], dpp_s<0x102, BW>(s), s);
+                s = mv_add<BW>(K[2], dpp_s<0x104, BW>(s), s);
+                s = mv_add<BW>(K[3], dpp_s<0x108, BW>(s), s);
+                const S2 c3 = G;
+                const S2 c2 = mv_add<BW>(Mrow, c3, readlane_s<BW>(s, 48));
+                const S2 c1 = mv_add<BW>(Mrow, c2, readlane_s<BW>(s, 32));
+                const S2 c0 = mv_add<BW>(Mrow, c1, readlane_s<BW>(s, 16));
+                in1[c] = mv_add<BW>(Mq, pick_row<BW>(row, c0, c1, c2, c3), dpp_s<0x101, BW>(s));
+                G = mv_add<BW>(Mrow, c0, readlane_s<BW>(s, 0));
+            }
         }
     }
     const S2 z0 = closure<BW>(Mn, G);
 
-    // true backward values (+ row 0 of M^(n-i) z0), scaled output
-    const gptr<TO> out = as_global(static_cast<TO *>(L.out));
+    // backward pass B, scaled by 1/K, and the stores
+    const gptr<T> out = as_global(static_cast<T *>(L.out));
     const double invK = L.invK;
+    {
+        const Mat Wq = pow_mat(pw, pb, E * (63 - lane));   // M^(E (63 - lane))
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-        if (c < last) {
-            // n - i = len_last + B (last - 1 - c) + 64 (3 - row) + 4 (15 - p) + (4 - j)
-            const S2 u = mv<BW>(Mlen, mv<BW>(load_mat(pb + 4 * (last - 1 - c)), z0));
-            const S2 w = mv<BW>(Mq, by_row<BW>(3 - row, m64r, u));
+        for (int c = NBB - 1; c >= 0; --c) {
+            if (c <= last) {
+                S2 s;
+                if (c < last) {
+                    // z0 carried from the line's top to the block's top
+                    const Mat Md = pow_mat(pw, pb, n - BLK * (c + 1));
+                    s = mv_add<BW>(Wq, mv<BW>(Md, z0), in1[c]);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                gst<TO>(out, lo + static_cast<unsigned>(B * c + j),
-                        from_f64<TO>((y[4 * c + j] + row0<BW>(P.e[4 - j], w)) * invK));
-        } else if (c == last) {
+                    for (int j = E - 1; j >= 0; --j) {
+                        s = rec<BW>(s, v[c][j], p1, p2);
+                        v[c][j] = s.x * invK;
+                    }
+                } else {
+                    // lanes of the last block: z0 carried over the valid
+                    // elements above the lane (d < BLK), as M^(d mod 256)
+                    // times M^(256 q) z0
+                    const int d = max(n - BLK * c - E * (lane + 1), 0);
+                    const int q = d / kWaveBlock;
+                    S2 zq = z0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = len_last - 4 * lane - j;   // n - i, in 1..len_last when valid
-                if (k >= 1)
-                    gst<TO>(out, B * c + 4 * lane + j, from_f64<TO>((y[4 * c + j] + row0<BW>(load_mat(pw + 4 * k), z0)) * invK));
+                    for (int qq = 1; qq < (BLK + kWaveBlock - 1) / kWaveBlock; ++qq) {
+                        const S2 t = mv<BW>(load_mat(pb + 4 * qq), z0);
+                        zq = keep_if<BW>(q == qq, t, zq);
+                    }
+                    s = mv_add<BW>(load_mat(pw + 4 * (d & (kWaveBlock - 1))), zq, in1[c]);
+#pragma unroll
+                    for (int j = E - 1; j >= 0; --j) {
+                        const S2 t = rec<BW>(s, v[c][j], p1, p2);
+                        s = keep_if<BW>(j < cnt, t, s);
+                        v[c][j] = s.x * invK;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < E; ++j) buf[lane * CH + j] = from_f64<T>(v[c][j]);
+                wave_sync();
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    const int idx = BLK * c + 64 * k + lane;
+                    const T val = buf[LPC * k * CH + wslot];
+                    if (c < last || idx < n) gst<T>(out, static_cast<unsigned>(idx), val);
+                }
+                wave_sync();
             }
         }
     }
@@ -314,24 +351,29 @@ __device__ __forceinline__ void wave_line(const Src &src, int li) {
 
 template <typename T, int BW, int NB>
 __global__ void __launch_bounds__(256) wave_ragged_kernel(const RaggedLines a, int first, int count) {
-    const int k = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    __shared__ __align__(16) T stage[4][Stage<T, WaveShape<NB>::E>::SIZE];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int k = blockIdx.x * 4 + w;
     if (k >= count) return;
-    wave_line<T, T, BW, NB>(RaggedSrc<T>{a}, first + k);
+    wave_line<T, BW, NB>(RaggedSrc<T>{a}, first + k, stage[w]);
 }
 
 template <typename T, int BW, int NB>
 __global__ void __launch_bounds__(256) wave_rows_kernel(const RowsInst *__restrict__ inst,
                                                         const int *__restrict__ map, int first,
                                                         int count) {
-    const int k = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    __shared__ __align__(16) T stage[4][Stage<T, WaveShape<NB>::E>::SIZE];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int k = blockIdx.x * 4 + w;
     if (k >= count) return;
-    wave_line<T, T, BW, NB>(RowsSrc<T>{inst, map}, first + k);
+    wave_line<T, BW, NB>(RowsSrc<T>{inst, map}, first + k, stage[w]);
 }
 
 template <typename T, int BW>
 hipError_t ragged_nb(int nb, const RaggedLines &a, int first, int count, hipStream_t s) {
     const dim3 grid((count + 3) / 4), block(256);
     switch (nb) {
+    case 1: hipLaunchKernelGGL((wave_ragged_kernel<T, BW, 1>), grid, block, 0, s, a, first, count); break;
     case 2: hipLaunchKernelGGL((wave_ragged_kernel<T, BW, 2>), grid, block, 0, s, a, first, count); break;
     case 4: hipLaunchKernelGGL((wave_ragged_kernel<T, BW, 4>), grid, block, 0, s, a, first, count); break;
     case 8: hipLaunchKernelGGL((wave_ragged_kernel<T, BW, 8>), grid, block, 0, s, a, first, count); break;
@@ -345,6 +387,7 @@ template <typename T, int BW>
 hipError_t rows_nb(int nb, const RowsInst *inst, const int *map, int first, int count, hipStream_t s) {
     const dim3 grid((count + 3) / 4), block(256);
     switch (nb) {
+    case 1: hipLaunchKernelGGL((wave_rows_kernel<T, BW, 1>), grid, block, 0, s, inst, map, first, count); break;
     case 2: hipLaunchKernelGGL((wave_rows_kernel<T, BW, 2>), grid, block, 0, s, inst, map, first, count); break;
     case 4: hipLaunchKernelGGL((wave_rows_kernel<T, BW, 4>), grid, block, 0, s, inst, map, first, count); break;
     case 8: hipLaunchKernelGGL((wave_rows_kernel<T, BW, 8>), grid, block, 0, s, inst, map, first, count); break;

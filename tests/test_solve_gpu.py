@@ -196,7 +196,7 @@ def test_line_kernels_every_length_class(monkeypatch, kernel, coef, dt):
     if kernel == "lds":
         assert "register_kernel" not in info
     else:
-        for nb in (2, 4, 8, 16):
+        for nb in (1, 2, 4, 8, 16):
             assert f"register_kernel(nb={nb}" in info
         assert "lds_kernel_lines=3 " in info     # 4097, 6000 and 9001
     b.mxs_compute(p)
