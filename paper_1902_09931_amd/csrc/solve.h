@@ -92,7 +92,7 @@ struct RowsInst {
 constexpr int kSeg = 32;
 constexpr int kColsThreads = 256;
 // phase B: kBGroups threads per column, kBCols columns per workgroup
-constexpr int kBGroups = 8;
+constexpr int kBGroups = 16;
 constexpr int kBCols = kColsThreads / kBGroups;
 
 struct ColsInst {
