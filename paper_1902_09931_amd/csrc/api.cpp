@@ -425,7 +425,7 @@ mxs_status mxs_create_1d_batch(int nbatch, const long long *offsets, int bc, int
         delete p;
         return st;
     }
-    const int W = p->threads * vec_elems(dtype);
+    const int W = p->threads * vec_elems(dtype) * kS1dVecs;
     const long long ntiles = (total + W - 1) / W;
     if (ntiles >= (1LL << 31)) {
         delete p;

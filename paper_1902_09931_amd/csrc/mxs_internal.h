@@ -243,6 +243,11 @@ struct Stencil2DArgs {
     int nt_store;           // 1: non-temporal output stores
 };
 
+// Vectors per thread in one tile of the batched 1D stencil (a tile is
+// threads * V * kS1dVecs elements, so one workgroup has that many bytes in
+// flight at once).
+constexpr int kS1dVecs = 2;
+
 struct Stencil1DArgs {
     const void *in;
     void *out;

@@ -212,14 +212,23 @@ extern "C" mxs_status mxs_create_cyclic_solve(int bw, const double *coef, int ge
         }
         std::vector<int> order(nbatch);
         std::iota(order.begin(), order.end(), 0);
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return len[a] > len[b]; });
+        // lines longer than the register kernel holds first, longest first
+        // (load balance of the persistent LDS kernel); then the register
+        // classes, largest first, each in memory order (neighbouring
+        // wavefronts read neighbouring lines)
+        auto lclass = [&](int k) { return len[k] > kWaveLineMax ? 32 : wave_nb(len[k]); };
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            const int ca = lclass(a), cb = lclass(b);
+            if (ca != cb) return ca > cb;
+            return ca == 32 && len[a] > len[b];
+        });
         if ((e = p->offsets.upload(offsets, sizeof(long long) * (nbatch + 1))) != hipSuccess ||
             (e = p->order.upload(order.data(), sizeof(int) * nbatch)) != hipSuccess) {
             delete p;
             return hip_fail(e, "line tables upload");
         }
         // lines longer than kWaveLineMax to the LDS kernel, the rest by
-        // register-block class (lengths are sorted, so classes are ranges)
+        // register-block class (each class is one range of the order)
         p->nlong = 0;
         if (force_lds_lines()) {
             p->nlong = nbatch;

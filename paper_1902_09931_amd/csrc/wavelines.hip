@@ -349,29 +349,29 @@ __device__ __forceinline__ void wave_line(const Src &src, int li, T *buf) {
     }
 }
 
+// One wavefront per workgroup: a workgroup's registers are released when its
+// own line is done, whatever the lengths of the lines beside it.
 template <typename T, int BW, int NB>
-__global__ void __launch_bounds__(256) wave_ragged_kernel(const RaggedLines a, int first, int count) {
-    __shared__ __align__(16) T stage[4][Stage<T, WaveShape<NB>::E>::SIZE];
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int k = blockIdx.x * 4 + w;
+__global__ void __launch_bounds__(64) wave_ragged_kernel(const RaggedLines a, int first, int count) {
+    __shared__ __align__(16) T stage[Stage<T, WaveShape<NB>::E>::SIZE];
+    const int k = blockIdx.x;
     if (k >= count) return;
-    wave_line<T, BW, NB>(RaggedSrc<T>{a}, first + k, stage[w]);
+    wave_line<T, BW, NB>(RaggedSrc<T>{a}, first + k, stage);
 }
 
 template <typename T, int BW, int NB>
-__global__ void __launch_bounds__(256) wave_rows_kernel(const RowsInst *__restrict__ inst,
-                                                        const int *__restrict__ map, int first,
-                                                        int count) {
-    __shared__ __align__(16) T stage[4][Stage<T, WaveShape<NB>::E>::SIZE];
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int k = blockIdx.x * 4 + w;
+__global__ void __launch_bounds__(64) wave_rows_kernel(const RowsInst *__restrict__ inst,
+                                                       const int *__restrict__ map, int first,
+                                                       int count) {
+    __shared__ __align__(16) T stage[Stage<T, WaveShape<NB>::E>::SIZE];
+    const int k = blockIdx.x;
     if (k >= count) return;
-    wave_line<T, BW, NB>(RowsSrc<T>{inst, map}, first + k, stage[w]);
+    wave_line<T, BW, NB>(RowsSrc<T>{inst, map}, first + k, stage);
 }
 
 template <typename T, int BW>
 hipError_t ragged_nb(int nb, const RaggedLines &a, int first, int count, hipStream_t s) {
-    const dim3 grid((count + 3) / 4), block(256);
+    const dim3 grid(count), block(64);
     switch (nb) {
     case 1: hipLaunchKernelGGL((wave_ragged_kernel<T, BW, 1>), grid, block, 0, s, a, first, count); break;
     case 2: hipLaunchKernelGGL((wave_ragged_kernel<T, BW, 2>), grid, block, 0, s, a, first, count); break;
@@ -385,7 +385,7 @@ hipError_t ragged_nb(int nb, const RaggedLines &a, int first, int count, hipStre
 
 template <typename T, int BW>
 hipError_t rows_nb(int nb, const RowsInst *inst, const int *map, int first, int count, hipStream_t s) {
-    const dim3 grid((count + 3) / 4), block(256);
+    const dim3 grid(count), block(64);
     switch (nb) {
     case 1: hipLaunchKernelGGL((wave_rows_kernel<T, BW, 1>), grid, block, 0, s, inst, map, first, count); break;
     case 2: hipLaunchKernelGGL((wave_rows_kernel<T, BW, 2>), grid, block, 0, s, inst, map, first, count); break;
