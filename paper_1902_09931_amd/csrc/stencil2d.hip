@@ -28,11 +28,9 @@ template <int NWX, int V> constexpr int halo_pad() {
     return NWX > 1 ? ((NWX - 1 + V - 1) / V) * V : 0;
 }
 
-// Input rows loaded per round (into LDS when NWX > 1): 4, or 2 for windows
-// along both axes accumulated in FP32 (measured faster there; FP64 and the
-// one-axis windows keep 4).
-template <typename A, int NWX, int NWY> constexpr int stage_rows() {
-    return sizeof(A) == 4 && NWX > 1 && NWY > 1 ? 2 : 4;
+// Input rows loaded per round (into LDS when NWX > 1).
+template <int NWY> constexpr int stage_rows() {
+    return 4;
 }
 
 template <typename A> __device__ __forceinline__ const A *coe_of(const Stencil2DArgs &a);
@@ -57,7 +55,7 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
     using A = typename St<T>::acc;
     constexpr int V = St<T>::V;
     constexpr int PAD = halo_pad<NWX, V>();
-    constexpr int G = stage_rows<A, NWX, NWY>();
+    constexpr int G = stage_rows<NWY>();
     constexpr int XW = V + NWX - 1;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -362,7 +360,7 @@ hipError_t launch_one(const Stencil2DArgs &a, int threads, hipStream_t s) {
     using A = typename St<T>::acc;
     constexpr int V = St<T>::V;
     const size_t lds = NWX > 1
-        ? static_cast<size_t>(stage_rows<A, NWX, NWY>()) * (2 * halo_pad<NWX, V>() + threads * V) * sizeof(A)
+        ? static_cast<size_t>(stage_rows<NWY>()) * (2 * halo_pad<NWX, V>() + threads * V) * sizeof(A)
         : 0;
     const int grid = a.nstrips * a.nchunks;
     hipLaunchKernelGGL((stencil2d_kernel<T, NWX, NWY>), dim3(grid), dim3(threads), lds, s, a);
@@ -398,7 +396,8 @@ size_t stencil2d_lds_bytes(int dtype, int nwx, int nwy, int threads) {
     const int V = dtype == F64 ? St<double>::V : dtype == F32 ? St<float>::V : St<bf16>::V;
     const int acc = dtype == F64 ? 8 : 4;
     const int pad = ((nwx - 1 + V - 1) / V) * V;
-    const int g = acc == 4 && nwy > 1 ? 2 : 4;   // stage_rows
+    const int g = 4;
+    (void)nwy;
     return static_cast<size_t>(g) * (2 * pad + threads * V) * acc;
 }
 
