@@ -337,6 +337,34 @@ def copy_ceiling(torch):
     return gbs
 
 
+def cpu_model():
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_ch(n, steps=2):
+    """The oracle (single thread) on the FP64 ADI Cahn-Hilliard step of an
+    n x n grid, in steps per second."""
+    import math
+    import oracle
+    from paper_1902_09931_amd import workloads as wl
+    c0 = wl.ch_initial(n, n, seed=2)
+    dx = 2 * math.pi / n
+    t0 = time.perf_counter()
+    oracle.ch_run(c0, c0, steps, dx, dx, 0.1 * dx * dx, 1.0, 0.01)
+    sec = time.perf_counter() - t0
+    return {"value": steps / sec, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps of the {n}^2 FP64 ADI Cahn-Hilliard step ({sec:.1f} s, "
+                      f"single-threaded C on {cpu_model()})"}
+
+
 def cpu_baseline(wl, n, rows):
     """The oracle (single thread) on the same eight stencils over a
     rows x n slice of the grid."""
@@ -352,7 +380,7 @@ def cpu_baseline(wl, n, rows):
     return {"value": pts / sec / 1e9, "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
             "sample": f"the eight stencils of one step on a {rows} x {n} slice "
                       f"({pts} point updates, {sec:.1f} s, single-threaded C, "
-                      f"{os.cpu_count()} host cores visible)"}
+                      f"{os.cpu_count()} host cores visible, {cpu_model()})"}
 
 
 def cpu_baseline_threads(wl, n, rows):
@@ -494,6 +522,7 @@ def main():
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(wl, n, rows=min(n, 3072))
         extra["cpu_baseline_all_cores"] = cpu_baseline_threads(wl, n, rows=min(n, 3072))
+        extra["cpu_baseline_ch_1024"] = cpu_baseline_ch(1024)
     if args.sections_only:     # no headline was measured: report the sections alone
         result = {"sections_only": True, "extra": extra}
     print(json.dumps(result), flush=True)
