@@ -25,12 +25,16 @@ struct RhsInst {
     float cdifff;
 };
 
+// Threads per workgroup of the right-hand side: at most kRhsThreads, at
+// least kRhsThreadsMin (a multiple of 64); a strip is threads * V columns.
 constexpr int kRhsThreads = 256;
+constexpr int kRhsThreadsMin = 64;
 
-// One launch over every instance of the table; map[b] is the instance of
-// workgroup b (nullptr: every workgroup belongs to instance 0).
+// One launch over every instance of the table with `threads` threads per
+// workgroup; map[b] is the instance of workgroup b (nullptr: every
+// workgroup belongs to instance 0).
 hipError_t launch_ch_rhs(int state_dtype, const RhsInst *inst, const int *map, int blocks,
-                         hipStream_t s);
+                         int threads, hipStream_t s);
 
 // Mass: per-instance double sums of a state buffer.
 struct MassInst {

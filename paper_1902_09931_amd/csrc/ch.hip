@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
 
     const int g = map ? map[blockIdx.x] : 0;
     const RhsInst &I = inst[g];
-    const int nt = kRhsThreads;
+    const int nt = blockDim.x;
     const int t = threadIdx.x;
     const int W = nt * V;
     const int rowlen = PAD + W + PAD;
@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(kRhsThreads) ch_rhs_kernel(const RhsInst *__re
         for (int v = 0; v < V; ++v) acc[k][v] = A(0);
 
     // halo columns per stage: G rows x 2*PAD, at most HPT per thread
-    constexpr int HPT = (G * 2 * PAD + kRhsThreads - 1) / kRhsThreads;
+    constexpr int HPT = (G * 2 * PAD + kRhsThreadsMin - 1) / kRhsThreadsMin;
     const int hcount = G * 2 * PAD;
 
     // issue the loads of C^n and C^{n-1} for the G input rows of stage s0
@@ -276,12 +276,13 @@ __global__ void __launch_bounds__(kMassThreads) mass_final_kernel(const MassInst
 }
 
 template <typename T, typename TW>
-hipError_t rhs_one(const RhsInst *inst, const int *map, int blocks, hipStream_t s) {
+hipError_t rhs_one(const RhsInst *inst, const int *map, int blocks, int threads, hipStream_t s) {
     using A = typename St<T>::acc;
     constexpr int V = St<T>::V;
     constexpr int PAD = V >= 2 ? V : 2;
-    const size_t lds = 2 * 4 * static_cast<size_t>(PAD + kRhsThreads * V + PAD) * sizeof(A);
-    hipLaunchKernelGGL((ch_rhs_kernel<T, TW>), dim3(blocks), dim3(kRhsThreads), lds, s, inst, map);
+    if (threads < kRhsThreadsMin || threads > kRhsThreads || threads % 64) return hipErrorInvalidValue;
+    const size_t lds = 2 * 4 * static_cast<size_t>(PAD + threads * V + PAD) * sizeof(A);
+    hipLaunchKernelGGL((ch_rhs_kernel<T, TW>), dim3(blocks), dim3(threads), lds, s, inst, map);
     return hipGetLastError();
 }
 
@@ -297,11 +298,11 @@ hipError_t mass_one(const MassInst *inst, const int *map, int ninst, int blocks,
 }  // namespace
 
 hipError_t launch_ch_rhs(int state_dtype, const RhsInst *inst, const int *map, int blocks,
-                         hipStream_t s) {
+                         int threads, hipStream_t s) {
     switch (state_dtype) {
-    case F64: return rhs_one<double, double>(inst, map, blocks, s);
-    case F32: return rhs_one<float, float>(inst, map, blocks, s);
-    case BF16: return rhs_one<bf16, float>(inst, map, blocks, s);
+    case F64: return rhs_one<double, double>(inst, map, blocks, threads, s);
+    case F32: return rhs_one<float, float>(inst, map, blocks, threads, s);
+    case BF16: return rhs_one<bf16, float>(inst, map, blocks, threads, s);
     default: return hipErrorInvalidValue;
     }
 }

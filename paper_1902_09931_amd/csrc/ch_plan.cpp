@@ -83,7 +83,7 @@ struct CHPlan final : mxs_plan_s {
     std::vector<RowRange> row_ranges;
     DevBuf partial, mass_out;
     double *mass_host = nullptr;
-    int rhs_blocks = 0, rhs_rows = 16, row_lines = 0, row_grid = 1, row_nw = 1, colsAC = 0, colsB = 0,
+    int rhs_blocks = 0, rhs_rows = 16, rhs_threads = kRhsThreads, row_lines = 0, row_grid = 1, row_nw = 1, colsAC = 0, colsB = 0,
         mass_blocks = 0, max_nx = 0;
     size_t row_lds = 0;
 
@@ -113,7 +113,7 @@ struct CHPlan final : mxs_plan_s {
 
     hipError_t enqueue(int r, hipStream_t s) {
         hipError_t e = launch_ch_rhs(dtype, static_cast<const RhsInst *>(rhs_d[r].ptr),
-                                     map_of(rhs_map), rhs_blocks, s);
+                                     map_of(rhs_map), rhs_blocks, rhs_threads, s);
         if (e != hipSuccess) return e;
         const RowsInst *ri = static_cast<const RowsInst *>(rows_d.ptr);
         if (row_ranges.empty())
@@ -188,7 +188,7 @@ struct CHPlan final : mxs_plan_s {
         auto tiles = [&](int r) {
             long long t = 0;
             for (const Inst &I : inst)
-                t += static_cast<long long>((I.nx + kRhsThreads * Vs - 1) / (kRhsThreads * Vs)) *
+                t += static_cast<long long>((I.nx + rhs_threads * Vs - 1) / (rhs_threads * Vs)) *
                      ((I.ny + r - 1) / r);
             return t;
         };
@@ -204,7 +204,7 @@ struct CHPlan final : mxs_plan_s {
             RhsInst ri{};
             ri.nx = I.nx;
             ri.ny = I.ny;
-            ri.nstrips = (I.nx + kRhsThreads * Vs - 1) / (kRhsThreads * Vs);
+            ri.nstrips = (I.nx + rhs_threads * Vs - 1) / (rhs_threads * Vs);
             ri.rows = rows;
             ri.nchunks = (I.ny + rows - 1) / rows;
             ri.blk0 = blk;
@@ -257,15 +257,18 @@ struct CHPlan final : mxs_plan_s {
             }
     }
 
-    // Chooses the right-hand side chunk height and the wavefronts per row
-    // solve by timing whole steps.  The timed steps rewrite only the buffer
+    // Chooses the right-hand side chunk height and workgroup size and the
+    // wavefronts per row solve by timing whole steps.  The timed steps
+    // rewrite only the buffer
     // that the next step overwrites anyway (C^{n+1}) and the plan's scratch,
     // and do not advance the step count.
     mxs_status autotune(hipStream_t s) override {
         const int r = static_cast<int>(steps % 3);
-        int best_rows = rhs_rows, best_w = row_nw;
+        int best_rows = rhs_rows, best_w = row_nw, best_threads = rhs_threads;
         double best_t = 1e30;
+        for (int threads : {256, 128, 64})
         for (int rows : {4, 8, 16, 32}) {
+            rhs_threads = threads;
             mxs_status st = build_rhs(rows);
             if (st) return st;
             for (int w : {1, 2, 4}) {
@@ -278,17 +281,19 @@ struct CHPlan final : mxs_plan_s {
                     best_t = t;
                     best_rows = rows;
                     best_w = w;
+                    best_threads = threads;
                 }
             }
         }
         set_row_waves(best_w);
         drop_graphs();
+        rhs_threads = best_threads;
         return build_rhs(best_rows);
     }
 
     void info(char *buf, int len) const override {
-        int n = snprintf(buf, len, "ch instances=%d dtype=%d rhs_rows=%d rhs_blocks=%d cols_blocks=%d",
-                         ninst(), dtype, rhs_rows, rhs_blocks, colsAC);
+        int n = snprintf(buf, len, "ch instances=%d dtype=%d rhs_rows=%d rhs_threads=%d rhs_blocks=%d cols_blocks=%d",
+                         ninst(), dtype, rhs_rows, rhs_threads, rhs_blocks, colsAC);
         if (row_ranges.empty() && n < len)
             n += snprintf(buf + n, len - n, " row_kernel=lds row_waves=%d row_grid=%d", row_nw, row_grid);
         for (size_t q = 0; q < row_ranges.size() && n < len; ++q)
