@@ -275,7 +275,7 @@ struct CHPlan final : mxs_plan_s {
                 if (line_lds_bytes(max_nx, w) > static_cast<size_t>(device_lds_limit())) continue;
                 if (!row_ranges.empty() && w != row_nw) continue;   // no LDS kernel to shape
                 set_row_waves(w);
-                const double t = time_launches([&] { return enqueue(r, s); }, s, 1, 3);
+                const double t = time_launches([&] { return enqueue(r, s); }, s, 2, 10);
                 if (t < 0) return hip_fail(hipGetLastError(), "autotune launch");
                 if (t < best_t) {
                     best_t = t;
