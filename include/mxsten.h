@@ -202,13 +202,16 @@ mxs_status mxs_ch_steps_taken(mxs_plan plan, long long *nsteps);
 mxs_status mxs_ch_mass(mxs_plan plan, double *host_out, void *hip_stream);
 
 /* Choose the plan's launch layout by measurement: candidate layouts (rows
- * per workgroup, tile order, threads per workgroup, streaming stores for
- * stencils; workgroup shape for the ragged stencil) are each run a few
- * times on the plan's own buffers and the fastest is kept.  The output
- * buffer of the plan is written while tuning (with correct results).  Waits
- * for the stream.  Layouts found are remembered for the rest of the process
- * for plans of the same shape and kind.  Plans without tunable layouts
- * return MXS_OK unchanged. */
+ * per workgroup, tile order, threads per workgroup and streaming stores for
+ * 2D stencils; wavefronts per line for lines solved in LDS, longer than
+ * 4096 elements; right-hand-side chunk height and workgroup size for the
+ * Cahn-Hilliard step) are each run a few times on the plan's own buffers
+ * and the fastest is kept.  A stencil or solve plan writes its output
+ * buffer while tuning (with correct results); a Cahn-Hilliard plan rewrites
+ * only the buffer its next step overwrites and its scratch, and the step
+ * count is unchanged.  Waits for the stream.  Stencil layouts found are
+ * remembered for the rest of the process for plans of the same shape.
+ * Plans without tunable layouts return MXS_OK unchanged. */
 mxs_status mxs_autotune(mxs_plan plan, void *hip_stream);
 
 /* A one-line description of the plan's current launch layout, written to

@@ -258,37 +258,43 @@ struct CHPlan final : mxs_plan_s {
     }
 
     // Chooses the right-hand side chunk height and workgroup size and the
-    // wavefronts per row solve by timing whole steps.  The timed steps
-    // rewrite only the buffer
-    // that the next step overwrites anyway (C^{n+1}) and the plan's scratch,
-    // and do not advance the step count.
+    // wavefronts per row solve by timing whole steps: every candidate is
+    // timed in two passes and keeps its faster time (candidates differ by a
+    // few percent, about the spread of one timing).  The timed steps rewrite
+    // only the buffer that the next step overwrites anyway (C^{n+1}) and the
+    // plan's scratch, and do not advance the step count.
     mxs_status autotune(hipStream_t s) override {
         const int r = static_cast<int>(steps % 3);
-        int best_rows = rhs_rows, best_w = row_nw, best_threads = rhs_threads;
-        double best_t = 1e30;
+        struct Cand {
+            int threads, rows, w;
+            double t;
+        };
+        std::vector<Cand> cands;
         for (int threads : {256, 128, 64})
-        for (int rows : {4, 8, 16, 32}) {
-            rhs_threads = threads;
-            mxs_status st = build_rhs(rows);
-            if (st) return st;
-            for (int w : {1, 2, 4}) {
-                if (line_lds_bytes(max_nx, w) > static_cast<size_t>(device_lds_limit())) continue;
-                if (!row_ranges.empty() && w != row_nw) continue;   // no LDS kernel to shape
-                set_row_waves(w);
+            for (int rows : {4, 8, 16, 32})
+                for (int w : {1, 2, 4}) {
+                    if (line_lds_bytes(max_nx, w) > static_cast<size_t>(device_lds_limit())) continue;
+                    if (!row_ranges.empty() && w != row_nw) continue;   // no LDS kernel to shape
+                    cands.push_back({threads, rows, w, 1e30});
+                }
+        if (cands.empty()) return MXS_OK;
+        for (int pass = 0; pass < 2; ++pass)
+            for (Cand &c : cands) {
+                rhs_threads = c.threads;
+                mxs_status st = build_rhs(c.rows);
+                if (st) return st;
+                set_row_waves(c.w);
                 const double t = time_launches([&] { return enqueue(r, s); }, s, 2, 10);
                 if (t < 0) return hip_fail(hipGetLastError(), "autotune launch");
-                if (t < best_t) {
-                    best_t = t;
-                    best_rows = rows;
-                    best_w = w;
-                    best_threads = threads;
-                }
+                c.t = std::min(c.t, t);
             }
-        }
-        set_row_waves(best_w);
+        const Cand *best = &cands.front();
+        for (const Cand &c : cands)
+            if (c.t < best->t) best = &c;
+        set_row_waves(best->w);
         drop_graphs();
-        rhs_threads = best_threads;
-        return build_rhs(best_rows);
+        rhs_threads = best->threads;
+        return build_rhs(best->rows);
     }
 
     void info(char *buf, int len) const override {
