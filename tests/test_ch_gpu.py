@@ -6,6 +6,7 @@ storage: the error against the FP64 oracle, run from the same rounded
 initial data, is measured and held under the bounds stated in the tests.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -309,11 +310,11 @@ def test_autotune_keeps_the_state_and_parity():
 def test_ch_ensemble_64_reduced_precision_against_oracle(dt_name, bound20, bound500):
     """The 64-grid ensemble workload (N uniform over multiples of 32 in
     [256, 1024], FP32 or BF16 storage) against the FP64 oracle run from the
-    same rounded initial data: every 4th instance (by size) after 20 steps
-    and the 8 smallest after 500 steps, plus each instance's mass drift.
+    same rounded initial data: every instance after 20 steps and the 8
+    smallest after 500 steps, plus each instance's mass drift.
     Reduced-precision storage has no a-priori error bound; the bounds are
-    the measured errors with a margin (measured: FP32 8.4e-5 / 7.1e-4, BF16
-    3.1e-2 / 3.3e-1).  With dt = 0.1 dx^2 the per-step increment of C is
+    the measured errors with a margin (measured: FP32 8.8e-5 / 7.0e-4, BF16
+    4.2e-2 / 3.3e-1).  With dt = 0.1 dx^2 the per-step increment of C is
     below the BF16 spacing over much of the grid, so BF16 storage stagnates
     and its error grows with the step count."""
     from concurrent.futures import ThreadPoolExecutor
@@ -327,7 +328,8 @@ def test_ch_ensemble_64_reduced_precision_against_oracle(dt_name, bound20, bound
     plan = b.mxs_ch_ensemble_create(sizes, sizes, dxs, dxs, dts, D, GAMMA, code(dt_name),
                                     [q[0] for q in bufs], [q[1] for q in bufs], [q[2] for q in bufs])
     order = np.argsort(sizes, kind="stable")
-    pool = ThreadPoolExecutor(8)      # the oracle releases the GIL inside its C calls
+    # the oracle releases the GIL inside its C calls
+    pool = ThreadPoolExecutor(max(1, min(16, len(os.sched_getaffinity(0)))))
 
     def state(k):
         _, cur = b.mxs_ch_state(plan, k)
@@ -340,7 +342,7 @@ def test_ch_ensemble_64_reduced_precision_against_oracle(dt_name, bound20, bound
         m0 = b.mxs_ch_mass(plan, len(sizes))
         b.mxs_ch_step(plan, 20, True)
         torch.cuda.synchronize()
-        pick20 = [int(k) for k in order[::4]]
+        pick20 = [int(k) for k in order]
         got20 = {k: state(k) for k in pick20}
         refs = dict(zip(pick20, pool.map(lambda k: oracle_run(k, 20), pick20)))
         err20 = {k: rel_err(got20[k], refs[k]) for k in pick20}
