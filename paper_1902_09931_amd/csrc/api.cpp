@@ -272,30 +272,42 @@ mxs_status Stencil2DPlan::autotune(hipStream_t s) {
         }
     }
     const TunedLayout start{a.rows, a.order, threads, a.nt_store};
-    TunedLayout best = start;
-    double best_t = 1e30;
+    // every candidate is timed in two passes and keeps its faster time (the
+    // best layouts differ by a few percent, about the spread of one timing)
+    struct Cand {
+        TunedLayout l;
+        double t;
+    };
+    std::vector<Cand> cands;
     const size_t lds_limit = static_cast<size_t>(device_lds_limit());
     for (int rows : {2, 4, 8, 16, 32, 64, 128}) {
         if (rows > 2 * a.ny && rows > 2) continue;
         for (int nthreads : {256, 128}) {
             if (stencil2d_lds_bytes(dtype, nwx, nwy, nthreads) > lds_limit) continue;
-            for (int order : {1, 0}) {
-                for (int nt : {1, 0}) {
-                    set_layout(rows, order, nthreads, nt);
-                    const double t = time_launches(
-                        [&] { return launch_stencil2d(dtype, nwx, nwy, a, threads, s); }, s, 2, 5);
-                    if (t < 0) {
-                        set_layout(start.rows, start.order, start.threads, start.nt);
-                        return hip_fail(hipGetLastError(), "autotune launch");
-                    }
-                    if (t < best_t) {
-                        best_t = t;
-                        best = TunedLayout{rows, order, nthreads, nt};
-                    }
-                }
-            }
+            for (int order : {1, 0})
+                for (int nt : {1, 0}) cands.push_back({TunedLayout{rows, order, nthreads, nt}, 1e30});
         }
     }
+    if (cands.empty()) return MXS_OK;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (Cand &c : cands) {
+            set_layout(c.l.rows, c.l.order, c.l.threads, c.l.nt);
+            const double t = time_launches(
+                [&] { return launch_stencil2d(dtype, nwx, nwy, a, threads, s); }, s, 2, 5);
+            if (t < 0) {
+                set_layout(start.rows, start.order, start.threads, start.nt);
+                return hip_fail(hipGetLastError(), "autotune launch");
+            }
+            c.t = std::min(c.t, t);
+        }
+    }
+    TunedLayout best = cands.front().l;
+    double best_t = cands.front().t;
+    for (const Cand &c : cands)
+        if (c.t < best_t) {
+            best_t = c.t;
+            best = c.l;
+        }
     set_layout(best.rows, best.order, best.threads, best.nt);
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tuned[key()] = best;
