@@ -48,7 +48,50 @@ struct SolvePlan final : mxs_plan_s {
     int nlines = 0, grid = 1, blocksAC = 0, blocksB = 0, nw = 1;
     size_t lds = 0, bytes = 0;
     bool dirty = true;
+    // ragged classes after the first run on streams of their own (default
+    // priority), forked from and joined back to the caller's stream: the
+    // classes touch disjoint lines, and the smaller ones then fill the gaps
+    // of the largest instead of each ending in a partly filled round
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> side_done;
+    hipEvent_t forked = nullptr;
     SolvePlan() : mxs_plan_s(KIND_SOLVE) {}
+    ~SolvePlan() override {
+        for (hipStream_t st : side) (void)hipStreamDestroy(st);
+        for (hipEvent_t ev : side_done) (void)hipEventDestroy(ev);
+        if (forked) (void)hipEventDestroy(forked);
+    }
+
+    hipError_t ensure_side(size_t n) {
+        if (!forked) {
+            hipError_t e = hipEventCreateWithFlags(&forked, hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+        while (side.size() < n) {
+            hipStream_t st = nullptr;
+            hipEvent_t ev = nullptr;
+            hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+            if (e != hipSuccess) return e;
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                (void)hipStreamDestroy(st);
+                return e;
+            }
+            side.push_back(st);
+            side_done.push_back(ev);
+        }
+        return hipSuccess;
+    }
+
+    // launch k of the ragged solve (0: the lines of the LDS kernel when there
+    // are any, then the register classes, largest first)
+    hipError_t ragged_launch(size_t k, hipStream_t st) {
+        if (nlong > 0) {
+            if (k == 0) return launch_ragged_lines(dtype, bw, rl, nw, grid, lds, st);
+            --k;
+        }
+        return launch_wave_ragged(dtype, bw, wave[k].nb, rl, wave[k].first, wave[k].count, st);
+    }
 
     mxs_status set_io(const void *rhs, void *x) {
         if (!rhs || !x) return fail(MXS_ERR_INVALID_ARG, "rhs/x must be device pointers");
@@ -67,9 +110,21 @@ struct SolvePlan final : mxs_plan_s {
     mxs_status compute(hipStream_t s) override {
         hipError_t e = hipSuccess;
         if (geometry == MXS_LINES_RAGGED) {
-            if (nlong > 0) e = launch_ragged_lines(dtype, bw, rl, nw, grid, lds, s);
-            for (size_t q = 0; q < wave.size() && e == hipSuccess; ++q)
-                e = launch_wave_ragged(dtype, bw, wave[q].nb, rl, wave[q].first, wave[q].count, s);
+            const size_t nl = (nlong > 0 ? 1 : 0) + wave.size();
+            if (nl <= 1) {
+                if (nl == 1) e = ragged_launch(0, s);
+            } else {
+                e = ensure_side(nl - 1);
+                if (e == hipSuccess) e = hipEventRecord(forked, s);
+                for (size_t k = 1; k < nl && e == hipSuccess; ++k) {
+                    hipStream_t st = side[k - 1];
+                    e = hipStreamWaitEvent(st, forked, 0);
+                    if (e == hipSuccess) e = ragged_launch(k, st);
+                    if (e == hipSuccess) e = hipEventRecord(side_done[k - 1], st);
+                }
+                if (e == hipSuccess) e = ragged_launch(0, s);
+                for (size_t k = 1; k < nl && e == hipSuccess; ++k) e = hipStreamWaitEvent(s, side_done[k - 1], 0);
+            }
         } else if (geometry == MXS_LINES_ROWS) {
             if (dirty) {
                 e = hipMemcpyAsync(table.ptr, &rows, sizeof rows, hipMemcpyHostToDevice, s);
