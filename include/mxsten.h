@@ -25,7 +25,8 @@
  *     "host" are read during the call only (the plan keeps its own copies).
  *   - Streams are hipStream_t values passed as void*; NULL is the default
  *     stream.  Compute and step calls only enqueue work; they return before
- *     it finishes.  Only mxs_ch_mass waits for its stream.
+ *     it finishes.  Only mxs_ch_mass, mxs_ch_coarsening and mxs_autotune
+ *     wait for their stream.
  *   - Every call returns an mxs_status.  No call aborts or prints; on error
  *     mxs_last_error() returns a message for the calling thread.
  *   - Plans are not thread-safe: one plan is used by one thread at a time.
@@ -145,7 +146,10 @@ mxs_status mxs_compute(mxs_plan plan, void *hip_stream);
  * solve plan, rhs and x are exchanged. */
 mxs_status mxs_swap(mxs_plan plan);
 
-/* Point the plan at other input/output buffers of the same shape. */
+/* Point the plan at other input/output buffers of the same shape.  A grid
+ * solve plan (MXS_LINES_ROWS or MXS_LINES_COLS) uploads its two instance
+ * tables here with blocking host-to-device copies, so that mxs_compute and
+ * mxs_swap themselves never copy from host memory. */
 mxs_status mxs_set_io(mxs_plan plan, const void *in, void *out);
 
 /* ------------------------------------------------------------------------
@@ -200,6 +204,20 @@ mxs_status mxs_ch_steps_taken(mxs_plan plan, long long *nsteps);
  * host_out[0 .. count-1].  Waits for the stream.  MXS_ERR_NONFINITE when a
  * sum is NaN or Inf. */
 mxs_status mxs_ch_mass(mxs_plan plan, double *host_out, void *hip_stream);
+
+/* Coarsening diagnostics of instance k's current state C^n (Sec. 5.3):
+ *   s  = 1 / (1 - <C^2>), <.> the spatial average by Simpson's rule (on the
+ *        periodic grid: node weights 2/3 and 4/3 alternating along each
+ *        axis, starting with 2/3 at index 0);
+ *   k1 = sum |C^(k)|^2 / sum |k|^-1 |C^(k)|^2 over the nonzero wavevectors
+ *        k = (2 pi mx / (nx dx), 2 pi my / (ny dy)) of the grid's discrete
+ *        Fourier transform (mx, my in -n/2+1 .. n/2).
+ * Written to *s_out and *k1_out (host; either may be NULL).  Both sums in
+ * double.  Needs nx and ny powers of two, at most 4096, else
+ * MXS_ERR_UNSUPPORTED.  The plan allocates its transform scratch (16 bytes
+ * per grid point) on the first call.  Waits for the stream. */
+mxs_status mxs_ch_coarsening(mxs_plan plan, int k, double *s_out, double *k1_out,
+                             void *hip_stream);
 
 /* Choose the plan's launch layout by measurement: candidate layouts (rows
  * per workgroup, tile order, threads per workgroup and streaming stores for

@@ -54,11 +54,17 @@ def lib():
                                   _f64p, _f64p, _f64p]
         L.orc_ch_run.argtypes = [_ll, _ll, _dbl, _dbl, _dbl, _dbl, _dbl, _int, _ll,
                                  _f64p, _f64p]
+        L.orc_ch_step_stored.argtypes = [_ll, _ll, _dbl, _dbl, _dbl, _dbl, _dbl, _int, _int,
+                                         _f64p, _f64p, _f64p]
+        L.orc_ch_run_stored.argtypes = [_ll, _ll, _dbl, _dbl, _dbl, _dbl, _dbl, _int, _int, _ll,
+                                        _f64p, _f64p]
+        L.orc_round_storage.argtypes = [_f64p, _f64p, _ll, _int]
         L.orc_sum.argtypes = [_f64p, _ll]
         L.orc_sum.restype = _dbl
         for name in ("orc_stencil2d", "orc_stencil2d_at", "orc_stencil1d_batch",
                      "orc_cyclic_solve_batch", "orc_cyclic_solve_grid", "orc_ch_step",
-                     "orc_ch_run"):
+                     "orc_ch_run", "orc_ch_step_stored", "orc_ch_run_stored",
+                     "orc_round_storage"):
             getattr(L, name).restype = _int
         _lib = L
     return _lib
@@ -188,6 +194,44 @@ def ch_run(c_prev, c_cur, nsteps, dx, dy, dt, D=1.0, gamma=0.01, nonlinear=True)
     ny, nx = cc.shape
     _check(lib().orc_ch_run(nx, ny, dx, dy, dt, D, gamma, int(bool(nonlinear)),
                             int(nsteps), cp, cc), "ch_run")
+    return cp, cc
+
+
+STORAGE = {"f64": 0, "f32": 1, "bf16": 2}
+
+
+def round_storage(x, storage):
+    """x rounded to the storage dtype ("f32" or "bf16"), nearest value, ties
+    to even, in one step from double."""
+    x = _f64(x)
+    y = np.empty_like(x)
+    _check(lib().orc_round_storage(x.ravel(), y.ravel(), x.size, STORAGE[storage]),
+           "round_storage")
+    return y
+
+
+def ch_step_stored(c_prev, c_cur, dx, dy, dt, storage, D=1.0, gamma=0.01, nonlinear=True):
+    """One ADI step (Sec. 5.1) in double arithmetic whose stored quantities
+    are rounded as a reduced-precision implementation stores them: the
+    right-hand side R and the x-sweep result w to float, C^{n+1} to the
+    storage dtype ("f32" or "bf16"; "f64" is ch_step)."""
+    cp = _f64(c_prev)
+    cc = _f64(c_cur)
+    ny, nx = cc.shape
+    out = np.zeros_like(cc)
+    _check(lib().orc_ch_step_stored(nx, ny, dx, dy, dt, D, gamma, int(bool(nonlinear)),
+                                    STORAGE[storage], cp, cc, out), "ch_step_stored")
+    return out
+
+
+def ch_run_stored(c_prev, c_cur, nsteps, dx, dy, dt, storage, D=1.0, gamma=0.01,
+                  nonlinear=True):
+    """nsteps of ch_step_stored; returns (C^{n-1}, C^n)."""
+    cp = _f64(c_prev).copy()
+    cc = _f64(c_cur).copy()
+    ny, nx = cc.shape
+    _check(lib().orc_ch_run_stored(nx, ny, dx, dy, dt, D, gamma, int(bool(nonlinear)),
+                                   STORAGE[storage], int(nsteps), cp, cc), "ch_run_stored")
     return cp, cc
 
 

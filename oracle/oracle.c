@@ -427,9 +427,65 @@ static void laplacian_5x5(double dx, double dy, double *w)
     }
 }
 
+/* Rounding of a double to the nearest float (ties to even), and to the
+ * nearest bfloat16 (8 significant bits, the exponent range of float; ties to
+ * even), each in one step from the double value.  Used by the stored-
+ * precision form of the step below. */
+static double round_f32(double v)
+{
+    return (double)(float)v;
+}
+
+static double round_bf16(double v)
+{
+    if (v == 0.0 || !isfinite(v))
+        return v;
+    int e;
+    double m = frexp(v, &e); /* v = m 2^e, 0.5 <= |m| < 1 */
+    if (e - 1 < -126)        /* below the smallest normal: fixed spacing 2^-133 */
+        return ldexp(nearbyint(ldexp(v, 133)), -133);
+    return ldexp(nearbyint(ldexp(m, 8)), e - 8);
+}
+
+static double round_storage(double v, int storage)
+{
+    return storage == 1 ? round_f32(v) : storage == 2 ? round_bf16(v) : v;
+}
+
+static int ch_step_impl(i64 nx, i64 ny, double dx, double dy, double dt,
+                        double D, double gamma, int nonlinear, int storage,
+                        const double *c_prev, const double *c_cur,
+                        double *c_next);
+
 int orc_ch_step(i64 nx, i64 ny, double dx, double dy, double dt, double D,
                 double gamma, int nonlinear, const double *c_prev,
                 const double *c_cur, double *c_next)
+{
+    return ch_step_impl(nx, ny, dx, dy, dt, D, gamma, nonlinear, 0, c_prev,
+                        c_cur, c_next);
+}
+
+/* The same step with the stored quantities rounded as a reduced-precision
+ * implementation stores them (the mixed-precision reading: state fields in
+ * the storage dtype, intermediate right-hand side and x-sweep result in
+ * float, all arithmetic in double): storage = 1 (float state) or 2
+ * (bfloat16 state); R and w are rounded to float, C^{n+1} to the storage
+ * dtype.  storage = 0 is orc_ch_step. */
+int orc_ch_step_stored(i64 nx, i64 ny, double dx, double dy, double dt,
+                       double D, double gamma, int nonlinear, int storage,
+                       const double *c_prev, const double *c_cur,
+                       double *c_next)
+{
+    if (storage < 0 || storage > 2)
+        return -1;
+    return ch_step_impl(nx, ny, dx, dy, dt, D, gamma, nonlinear, storage,
+                        c_prev, c_cur, c_next);
+}
+
+static int ch_step_impl(i64 nx, i64 ny, double dx, double dy, double dt,
+                        double D, double gamma, int nonlinear, int storage,
+                        const double *c_prev, const double *c_cur,
+                        double *c_next)
 {
     const i64 npts = nx * ny;
     if (nx < 5 || ny < 5)
@@ -465,6 +521,9 @@ int orc_ch_step(i64 nx, i64 ny, double dx, double dy, double dt, double D,
     for (i64 k = 0; k < npts; ++k)
         rhs[k] = -2.0 / 3.0 * (c_cur[k] - c_prev[k]) - a * bih[k]
                  + 2.0 / 3.0 * D * dt * lap[k];
+    if (storage)
+        for (i64 k = 0; k < npts; ++k)
+            rhs[k] = round_f32(rhs[k]);
 
     {
         const double bx = a / (dx * dx * dx * dx);
@@ -473,12 +532,15 @@ int orc_ch_step(i64 nx, i64 ny, double dx, double dy, double dt, double D,
         const double ly[5] = {by, -4.0 * by, 1.0 + 6.0 * by, -4.0 * by, by};
         if (orc_cyclic_solve_grid(2, lx, 0, nx, ny, nx, rhs, w))
             goto done;
+        if (storage)
+            for (i64 k = 0; k < npts; ++k)
+                w[k] = round_f32(w[k]);
         if (orc_cyclic_solve_grid(2, ly, 1, nx, ny, nx, w, v))
             goto done;
     }
 
     for (i64 k = 0; k < npts; ++k)
-        c_next[k] = cbar[k] + v[k];
+        c_next[k] = round_storage(cbar[k] + v[k], storage);
     st = 0;
 done:
     free(cbar);
@@ -490,19 +552,19 @@ done:
     return st;
 }
 
-/* nsteps steps of orc_ch_step, rotating the two time levels; on return
- * c_prev/c_cur hold C^{n-1}, C^n of the last step. */
-int orc_ch_run(i64 nx, i64 ny, double dx, double dy, double dt, double D,
-               double gamma, int nonlinear, i64 nsteps, double *c_prev,
-               double *c_cur)
+/* nsteps steps of orc_ch_step_stored, rotating the two time levels; on
+ * return c_prev/c_cur hold C^{n-1}, C^n of the last step. */
+int orc_ch_run_stored(i64 nx, i64 ny, double dx, double dy, double dt,
+                      double D, double gamma, int nonlinear, int storage,
+                      i64 nsteps, double *c_prev, double *c_cur)
 {
     const i64 npts = nx * ny;
     double *nxt = (double *)malloc(sizeof(double) * npts);
     if (!nxt)
         return -1;
     for (i64 s = 0; s < nsteps; ++s) {
-        if (orc_ch_step(nx, ny, dx, dy, dt, D, gamma, nonlinear, c_prev,
-                        c_cur, nxt)) {
+        if (orc_ch_step_stored(nx, ny, dx, dy, dt, D, gamma, nonlinear,
+                               storage, c_prev, c_cur, nxt)) {
             free(nxt);
             return -1;
         }
@@ -510,6 +572,26 @@ int orc_ch_run(i64 nx, i64 ny, double dx, double dy, double dt, double D,
         memcpy(c_cur, nxt, sizeof(double) * npts);
     }
     free(nxt);
+    return 0;
+}
+
+/* nsteps steps of orc_ch_step (double precision throughout). */
+int orc_ch_run(i64 nx, i64 ny, double dx, double dy, double dt, double D,
+               double gamma, int nonlinear, i64 nsteps, double *c_prev,
+               double *c_cur)
+{
+    return orc_ch_run_stored(nx, ny, dx, dy, dt, D, gamma, nonlinear, 0,
+                             nsteps, c_prev, c_cur);
+}
+
+/* The rounding of n values to a storage dtype as the stored-precision step
+ * applies it (storage = 1 float, 2 bfloat16); exported for its pins. */
+int orc_round_storage(const double *x, double *y, i64 n, int storage)
+{
+    if (storage < 1 || storage > 2)
+        return -1;
+    for (i64 k = 0; k < n; ++k)
+        y[k] = round_storage(x[k], storage);
     return 0;
 }
 

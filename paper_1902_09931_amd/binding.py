@@ -83,6 +83,7 @@ _SIGS = {
     "mxs_ch_state": [_vp, _int, ctypes.POINTER(_vp), ctypes.POINTER(_vp)],
     "mxs_ch_steps_taken": [_vp, _llp],
     "mxs_ch_mass": [_vp, _dp, _vp],
+    "mxs_ch_coarsening": [_vp, _int, _dp, _dp, _vp],
     "mxs_destroy": [_vp],
     "mxs_autotune": [_vp, _vp],
     "mxs_plan_info": [_vp, ctypes.c_char_p, _int],
@@ -258,3 +259,10 @@ def mxs_ch_mass(plan, count=1, stream=None):
     out = (ctypes.c_double * count)()
     _check(_lib.mxs_ch_mass(plan, out, _stream(stream)))
     return [out[k] for k in range(count)]
+
+
+def mxs_ch_coarsening(plan, k=0, stream=None):
+    """Coarsening diagnostics (s, k1) of instance k's current state."""
+    sv, kv = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.mxs_ch_coarsening(plan, k, ctypes.byref(sv), ctypes.byref(kv), _stream(stream)))
+    return sv.value, kv.value

@@ -10,6 +10,7 @@
 // consecutive steps; the plan keeps one instance table (and one captured
 // HIP graph) per rotation.
 #include "ch.h"
+#include "diag.h"
 #include "plans.h"
 #include "solve.h"
 
@@ -179,6 +180,43 @@ struct CHPlan final : mxs_plan_s {
         return finite ? MXS_OK : fail(MXS_ERR_NONFINITE, "the mass is not finite");
     }
 
+    // Coarsening diagnostics of instance k's C^n (Sec. 5.3); the scratch of
+    // the transform is allocated on the first call and kept by the plan.
+    DevBuf diag_spec, diag_partial, diag_out;
+    mxs_status coarsening(int k, double *s_out, double *k1_out, hipStream_t s) {
+        const Inst &I = inst[k];
+        if (!diag_shape_ok(I.nx, I.ny))
+            return fail(MXS_ERR_UNSUPPORTED, "coarsening diagnostics need power-of-two sides up to %d (got %d x %d)",
+                        kDiagMaxSide, I.nx, I.ny);
+        const size_t spec = sizeof(double2) * static_cast<size_t>(I.nx) * I.ny;
+        const size_t part = sizeof(double) * (static_cast<size_t>(I.ny) + 2 * I.nx);
+        hipError_t e = hipSuccess;
+        if (diag_spec.bytes < spec) e = diag_spec.alloc(spec);
+        if (e == hipSuccess && diag_partial.bytes < part) e = diag_partial.alloc(part);
+        if (e == hipSuccess && !diag_out.ptr) e = diag_out.alloc(3 * sizeof(double));
+        if (e != hipSuccess) return hip_fail(e, "diagnostics scratch allocation");
+        DiagArgs d{};
+        d.c = I.buf[(steps % 3 + 1) % 3];
+        d.nx = I.nx;
+        d.ny = I.ny;
+        d.kx0 = 2.0 * M_PI / (I.nx * I.dx);
+        d.ky0 = 2.0 * M_PI / (I.ny * I.dy);
+        d.spec = static_cast<double2 *>(diag_spec.ptr);
+        d.partial = static_cast<double *>(diag_partial.ptr);
+        d.out = static_cast<double *>(diag_out.ptr);
+        double h[3];
+        e = launch_coarsening(dtype, d, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(h, d.out, sizeof h, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "coarsening diagnostics");
+        const double mean_c2 = h[0] / (static_cast<double>(I.nx) * I.ny);
+        if (s_out) *s_out = 1.0 / (1.0 - mean_c2);
+        if (k1_out) *k1_out = h[1] / h[2];
+        return std::isfinite(mean_c2) && std::isfinite(h[1]) && std::isfinite(h[2])
+                   ? MXS_OK
+                   : fail(MXS_ERR_NONFINITE, "the diagnostics are not finite");
+    }
+
     // Right-hand side tables for row chunks of `rows` rows (0: pick a height
     // that keeps several workgroups per CU).
     mxs_status build_rhs(int rows) {
@@ -264,6 +302,9 @@ struct CHPlan final : mxs_plan_s {
     // only the buffer that the next step overwrites anyway (C^{n+1}) and the
     // plan's scratch, and do not advance the step count.
     mxs_status autotune(hipStream_t s) override {
+        // the candidates rebuild the tables that captured graphs point at:
+        // drop the graphs first, so that no exit path leaves a stale one
+        drop_graphs();
         const int r = static_cast<int>(steps % 3);
         struct Cand {
             int threads, rows, w;
@@ -292,7 +333,6 @@ struct CHPlan final : mxs_plan_s {
         for (const Cand &c : cands)
             if (c.t < best->t) best = &c;
         set_row_waves(best->w);
-        drop_graphs();
         rhs_threads = best->threads;
         return build_rhs(best->rows);
     }
@@ -551,6 +591,13 @@ mxs_status mxs_ch_steps_taken(mxs_plan plan, long long *nsteps) {
     if (!nsteps) return fail(MXS_ERR_INVALID_ARG, "nsteps is NULL");
     *nsteps = p->steps;
     return MXS_OK;
+}
+
+mxs_status mxs_ch_coarsening(mxs_plan plan, int k, double *s_out, double *k1_out, void *hip_stream) {
+    CHPlan *p = as_ch(plan);
+    if (!p) return fail(MXS_ERR_BAD_HANDLE, "not a Cahn-Hilliard plan");
+    if (k < 0 || k >= p->ninst()) return fail(MXS_ERR_INVALID_ARG, "instance %d out of range", k);
+    return p->coarsening(k, s_out, k1_out, static_cast<hipStream_t>(hip_stream));
 }
 
 mxs_status mxs_ch_mass(mxs_plan plan, double *host_out, void *hip_stream) {

@@ -121,10 +121,20 @@ hipError_t launch_ragged_lines(int dtype, int bw, const RaggedLines &a, int nw, 
 // belong to instance 0.
 hipError_t launch_rows(int dtype, int bw, const RowsInst *inst, const int *map, int nlines, int nw,
                        int grid, size_t lds, hipStream_t s);
-// Register kernel over lines first .. first + count - 1 (sorted positions for
-// ragged lines, global line indices for rows), each at most 256 nb elements.
-hipError_t launch_wave_ragged(int dtype, int bw, int nb, const RaggedLines &a, int first, int count,
-                              hipStream_t s);
+// A work unit of the register kernel for ragged lines: `count` consecutive
+// lines (positions first .. first + count - 1 of the sorted order) of length
+// class nb, at most kWaveNBMax / nb of them.
+struct WaveUnit {
+    int first;
+    int count;
+    int nb;
+    int pad;
+};
+// Every work unit in one launch (one wavefront per unit).
+hipError_t launch_wave_units(int dtype, int bw, const RaggedLines &a, const WaveUnit *units, int nunits,
+                             hipStream_t s);
+// Register kernel over the rows first .. first + count - 1 (global line
+// indices), each at most 256 nb elements.
 hipError_t launch_wave_rows(int dtype, int bw, int nb, const RowsInst *inst, const int *map, int first,
                             int count, hipStream_t s);
 // epilogue: 0 = x = A^-1 rhs; 1 = Cahn-Hilliard update x = 2 cur - prev + A^-1 rhs.

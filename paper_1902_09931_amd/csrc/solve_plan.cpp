@@ -32,123 +32,98 @@ struct SolvePlan final : mxs_plan_s {
     CyclicFactor f;
     // ragged
     RaggedLines rl{};
-    DevBuf offsets, order;
-    // rows / cols
+    DevBuf offsets, order, units;
+    // rows / cols: the instance table of the current (rhs, x) pair in
+    // tables[cur], of the swapped pair in tables[1 - cur]; both are uploaded
+    // when the pointers are set, so that compute() only launches (it can be
+    // captured into a graph) and swap() only flips cur
     RowsInst rows{};
     ColsInst cols{};
-    DevBuf table, carry, pow;
-    // register kernel: (blocks per line, first line, line count) per class;
-    // ragged lines longer than kWaveLineMax (the first nlong in sorted
-    // order) go to the LDS kernel
+    DevBuf tables[2], carry, pow;
+    int cur = 0;
+    // register kernel classes (blocks per line, first line, line count), for
+    // plan_info; ragged lines longer than kWaveLineMax (the first nlong in
+    // sorted order) go to the LDS kernel, the others to one launch of the
+    // work-unit kernel
     struct WaveRange {
         int nb, first, count;
     };
     std::vector<WaveRange> wave;
+    int nunits = 0;
     int nlong = 0;
     int nlines = 0, grid = 1, blocksAC = 0, blocksB = 0, nw = 1;
     size_t lds = 0, bytes = 0;
-    bool dirty = true;
-    // ragged classes after the first run on streams of their own (default
-    // priority), forked from and joined back to the caller's stream: the
-    // classes touch disjoint lines, and the smaller ones then fill the gaps
-    // of the largest instead of each ending in a partly filled round
-    std::vector<hipStream_t> side;
-    std::vector<hipEvent_t> side_done;
-    hipEvent_t forked = nullptr;
     SolvePlan() : mxs_plan_s(KIND_SOLVE) {}
-    ~SolvePlan() override {
-        for (hipStream_t st : side) (void)hipStreamDestroy(st);
-        for (hipEvent_t ev : side_done) (void)hipEventDestroy(ev);
-        if (forked) (void)hipEventDestroy(forked);
-    }
 
-    hipError_t ensure_side(size_t n) {
-        if (!forked) {
-            hipError_t e = hipEventCreateWithFlags(&forked, hipEventDisableTiming);
-            if (e != hipSuccess) return e;
-        }
-        while (side.size() < n) {
-            hipStream_t st = nullptr;
-            hipEvent_t ev = nullptr;
-            hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-            if (e != hipSuccess) return e;
-            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-            if (e != hipSuccess) {
-                (void)hipStreamDestroy(st);
-                return e;
+    // Upload the instance tables of (rhs, x) and of the swapped pair
+    // (synchronous copies from host memory, before any launch uses them).
+    hipError_t upload_tables(const void *rhs, void *x) {
+        for (int k = 0; k < 2; ++k) {
+            const void *in = k == 0 ? rhs : x;
+            void *out = k == 0 ? x : const_cast<void *>(rhs);
+            hipError_t e;
+            if (geometry == MXS_LINES_ROWS) {
+                RowsInst ri = rows;
+                ri.in = in;
+                ri.out = out;
+                e = tables[k].upload(&ri, sizeof ri);
+            } else {
+                ColsInst ci = cols;
+                ci.rhs = in;
+                ci.x = out;
+                e = tables[k].upload(&ci, sizeof ci);
             }
-            side.push_back(st);
-            side_done.push_back(ev);
+            if (e != hipSuccess) return e;
         }
         return hipSuccess;
-    }
-
-    // launch k of the ragged solve (0: the lines of the LDS kernel when there
-    // are any, then the register classes, largest first)
-    hipError_t ragged_launch(size_t k, hipStream_t st) {
-        if (nlong > 0) {
-            if (k == 0) return launch_ragged_lines(dtype, bw, rl, nw, grid, lds, st);
-            --k;
-        }
-        return launch_wave_ragged(dtype, bw, wave[k].nb, rl, wave[k].first, wave[k].count, st);
     }
 
     mxs_status set_io(const void *rhs, void *x) {
         if (!rhs || !x) return fail(MXS_ERR_INVALID_ARG, "rhs/x must be device pointers");
         if (rhs != x && ranges_overlap(rhs, bytes, x, bytes))
             return fail(MXS_ERR_ALIAS, "rhs and x overlap without being the same buffer");
+        if (geometry != MXS_LINES_RAGGED) {
+            hipError_t e = upload_tables(rhs, x);
+            if (e != hipSuccess) return hip_fail(e, "solve table upload");
+        }
         rl.in = rhs;
         rl.out = x;
         rows.in = rhs;
         rows.out = x;
         cols.rhs = rhs;
         cols.x = x;
-        dirty = true;
+        cur = 0;
         return MXS_OK;
     }
 
     mxs_status compute(hipStream_t s) override {
         hipError_t e = hipSuccess;
         if (geometry == MXS_LINES_RAGGED) {
-            const size_t nl = (nlong > 0 ? 1 : 0) + wave.size();
-            if (nl <= 1) {
-                if (nl == 1) e = ragged_launch(0, s);
-            } else {
-                e = ensure_side(nl - 1);
-                if (e == hipSuccess) e = hipEventRecord(forked, s);
-                for (size_t k = 1; k < nl && e == hipSuccess; ++k) {
-                    hipStream_t st = side[k - 1];
-                    e = hipStreamWaitEvent(st, forked, 0);
-                    if (e == hipSuccess) e = ragged_launch(k, st);
-                    if (e == hipSuccess) e = hipEventRecord(side_done[k - 1], st);
-                }
-                if (e == hipSuccess) e = ragged_launch(0, s);
-                for (size_t k = 1; k < nl && e == hipSuccess; ++k) e = hipStreamWaitEvent(s, side_done[k - 1], 0);
-            }
+            if (nlong > 0) e = launch_ragged_lines(dtype, bw, rl, nw, grid, lds, s);
+            if (e == hipSuccess && nunits > 0)
+                e = launch_wave_units(dtype, bw, rl, static_cast<const WaveUnit *>(units.ptr), nunits, s);
         } else if (geometry == MXS_LINES_ROWS) {
-            if (dirty) {
-                e = hipMemcpyAsync(table.ptr, &rows, sizeof rows, hipMemcpyHostToDevice, s);
-                dirty = false;
-            }
-            const RowsInst *ti = static_cast<const RowsInst *>(table.ptr);
-            if (e == hipSuccess && !wave.empty())
+            const RowsInst *ti = static_cast<const RowsInst *>(tables[cur].ptr);
+            if (!wave.empty())
                 e = launch_wave_rows(dtype, bw, wave[0].nb, ti, nullptr, 0, nlines, s);
-            else if (e == hipSuccess)
+            else
                 e = launch_rows(dtype, bw, ti, nullptr, nlines, nw, grid, lds, s);
         } else {
-            if (dirty) {
-                e = hipMemcpyAsync(table.ptr, &cols, sizeof cols, hipMemcpyHostToDevice, s);
-                dirty = false;
-            }
-            if (e == hipSuccess)
-                e = launch_cols(dtype, dtype, bw, 0, static_cast<const ColsInst *>(table.ptr), nullptr,
-                                nullptr, blocksAC, blocksB, s);
+            e = launch_cols(dtype, dtype, bw, 0, static_cast<const ColsInst *>(tables[cur].ptr), nullptr,
+                            nullptr, blocksAC, blocksB, s);
         }
         return e == hipSuccess ? MXS_OK : hip_fail(e, "cyclic solve launch");
     }
     mxs_status swap() override {
         const void *r = rl.in;
-        return set_io(rl.out, const_cast<void *>(r));
+        rl.in = rl.out;
+        rl.out = const_cast<void *>(r);
+        rows.in = rl.in;
+        rows.out = rl.out;
+        cols.rhs = rl.in;
+        cols.x = rl.out;
+        cur = 1 - cur;
+        return MXS_OK;
     }
     mxs_status rebind(const void *in, void *out) override { return set_io(in, out); }
 
@@ -193,6 +168,8 @@ struct SolvePlan final : mxs_plan_s {
         if (geometry != MXS_LINES_COLS && lds_kernel && n < len)
             n += snprintf(buf + n, len - n, " lds_kernel_lines=%d waves_per_line=%d grid=%d lds=%zu",
                           geometry == MXS_LINES_RAGGED ? nlong : nlines, nw, grid, lds);
+        if (geometry == MXS_LINES_RAGGED && nunits > 0 && n < len)
+            n += snprintf(buf + n, len - n, " launches=%d units=%d", (nlong > 0) + 1, nunits);
         for (size_t q = 0; q < wave.size() && n < len; ++q)
             n += snprintf(buf + n, len - n, " register_kernel(nb=%d lines=%d)", wave[q].nb, wave[q].count);
     }
@@ -297,6 +274,20 @@ extern "C" mxs_status mxs_create_cyclic_solve(int bw, const double *coef, int ge
                 q = r;
             }
         }
+        // work units: consecutive lines of one class, kWaveNBMax / nb of
+        // them (the last unit of a class may hold fewer), largest class first
+        std::vector<WaveUnit> units;
+        for (const auto &w : p->wave) {
+            const int per = kWaveNBMax / w.nb;
+            for (int q = 0; q < w.count; q += per)
+                units.push_back({w.first + q, std::min(per, w.count - q), w.nb, 0});
+        }
+        p->nunits = static_cast<int>(units.size());
+        if (!units.empty() &&
+            (e = p->units.upload(units.data(), sizeof(WaveUnit) * units.size())) != hipSuccess) {
+            delete p;
+            return hip_fail(e, "line tables upload");
+        }
         p->rl.offsets = static_cast<const long long *>(p->offsets.ptr);
         p->rl.order = static_cast<const int *>(p->order.ptr);
         p->rl.nlines = p->nlong;
@@ -317,10 +308,6 @@ extern "C" mxs_status mxs_create_cyclic_solve(int bw, const double *coef, int ge
                         "line length %lld outside [%d, %lld]", n, minlen, kMaxLine);
         }
         p->bytes = grid_bytes(nx, ny, ld, dtype);
-        if ((st = p->set_io(rhs, x))) {
-            delete p;
-            return st;
-        }
         if (geometry == MXS_LINES_ROWS) {
             p->rows.ld = ld;
             p->rows.nx = nx;
@@ -333,7 +320,6 @@ extern "C" mxs_status mxs_create_cyclic_solve(int bw, const double *coef, int ge
             p->nmax = nx;
             if (nx <= kWaveLineMax && !force_lds_lines()) p->wave.push_back({wave_nb(nx), 0, ny});
             p->set_waves(line_waves(nx));
-            e = p->table.alloc(sizeof(RowsInst));
         } else {
             fill_cols_coef(p->f, bw, ny, &p->cols);
             p->cols.ld = ld;
@@ -345,12 +331,16 @@ extern "C" mxs_status mxs_create_cyclic_solve(int bw, const double *coef, int ge
             p->blocksAC = p->cols.nstrips * p->cols.nseg;
             p->blocksB = (nx + kBCols - 1) / kBCols;
             e = p->carry.alloc(sizeof(double) * 4 * static_cast<size_t>(nx) * p->cols.nseg);
-            if (e == hipSuccess) e = p->table.alloc(sizeof(ColsInst));
             p->cols.carry = static_cast<double *>(p->carry.ptr);
         }
         if (e != hipSuccess) {
             delete p;
             return hip_fail(e, "solve scratch allocation");
+        }
+        // the instance tables, now that every field but the pointers is set
+        if ((st = p->set_io(rhs, x))) {
+            delete p;
+            return st;
         }
     }
     if (p->lds > static_cast<size_t>(device_lds_limit())) {

@@ -145,28 +145,17 @@ template <typename T, int E> struct Stage {
     static constexpr int SIZE = 64 * CH;
 };
 
-// Solve line li with the wavefront of the calling lanes (all 64 active);
-// buf is the wavefront's LDS stage.
-template <typename T, int BW, int NB, class Src>
-__device__ __forceinline__ void wave_line(const Src &src, int li, T *buf) {
+// Request every element of a line of n elements (n <= 256 NB) into the
+// registers of the calling wavefront, none used yet: element BLK c + 64 k +
+// lane goes to raw[c][k] of lane `lane` (coalesced), clamped into the line
+// in the last block.
+template <typename T, int NB>
+__device__ __forceinline__ void wave_fetch(gptr<const T> in, int n,
+                                           T (&raw)[WaveShape<NB>::NBB][WaveShape<NB>::E]) {
     constexpr int E = WaveShape<NB>::E, NBB = WaveShape<NB>::NBB;
     constexpr int BLK = 64 * E;
-    constexpr int CH = Stage<T, E>::CH;
-    constexpr int LPC = 64 / E;   // lane chunks per 64 consecutive elements
     const int lane = threadIdx.x & 63;
-    const int row = lane >> 4, p = lane & 15;
-    const LineRef L = src.get(li);
-    const int n = L.n;
-    const gptr<const double> pw = as_global(L.pow);
-    const gptr<const double> pb = pw + 4 * (kWaveBlock + 1);
-    const double p1 = L.p1, p2 = L.p2;
     const int last = (n - 1) / BLK;
-
-    // every element of the line requested before any is used: element
-    // BLK c + 64 k + lane by lane `lane` (coalesced), clamped into the line
-    // in the last block
-    const gptr<const T> in = as_global(static_cast<const T *>(L.in));
-    T raw[NBB][E];
 #pragma unroll
     for (int c = 0; c < NBB; ++c) {
         if (c < last) {
@@ -177,6 +166,26 @@ __device__ __forceinline__ void wave_line(const Src &src, int li, T *buf) {
             for (int k = 0; k < E; ++k) raw[c][k] = gld<T>(in, min(BLK * c + 64 * k + lane, n - 1));
         }
     }
+}
+
+// Solve line L, whose elements wave_fetch has requested into raw, with the
+// wavefront of the calling lanes (all 64 active), and store it; buf is the
+// wavefront's LDS stage.
+template <typename T, int BW, int NB>
+__device__ __forceinline__ void wave_solve(const LineRef &L,
+                                           T (&raw)[WaveShape<NB>::NBB][WaveShape<NB>::E], T *buf) {
+    constexpr int E = WaveShape<NB>::E, NBB = WaveShape<NB>::NBB;
+    constexpr int BLK = 64 * E;
+    constexpr int CH = Stage<T, E>::CH;
+    constexpr int LPC = 64 / E;   // lane chunks per 64 consecutive elements
+    const int lane = threadIdx.x & 63;
+    const int row = lane >> 4, p = lane & 15;
+    const int n = L.n;
+    const gptr<const double> pw = as_global(L.pow);
+    const gptr<const double> pb = pw + 4 * (kWaveBlock + 1);
+    const double p1 = L.p1, p2 = L.p2;
+    const int last = (n - 1) / BLK;
+
     // element 64 k + lane of a block sits in chunk LPC k + lane / E, slot lane % E
     const int wslot = (lane / E) * CH + lane % E;
 
@@ -349,14 +358,100 @@ __device__ __forceinline__ void wave_line(const Src &src, int li, T *buf) {
     }
 }
 
-// One wavefront per workgroup: a workgroup's registers are released when its
-// own line is done, whatever the lengths of the lines beside it.
+// Solve line li of a source (rows of a grid table) with the calling
+// wavefront.
+template <typename T, int BW, int NB, class Src>
+__device__ __forceinline__ void wave_line(const Src &src, int li, T *buf) {
+    const LineRef L = src.get(li);
+    T raw[WaveShape<NB>::NBB][WaveShape<NB>::E];
+    wave_fetch<T, NB>(as_global(static_cast<const T *>(L.in)), L.n, raw);
+    wave_solve<T, BW, NB>(L, raw, buf);
+}
+
+// One work unit of ragged lines: `count` consecutive lines (at most K =
+// kWaveNBMax / NB) of length class NB, solved one after the other by the
+// calling wavefront, every element of line q + 1 requested while line q is
+// solved.  Requests past the unit's last line repeat that line (its elements
+// come from the cache) so that the request sequence, and with it the waits
+// for each line's elements, is the same in every unit.  Double-precision
+// pentadiagonal lines of class 8 are not prefetched: the second line's
+// registers would not fit beside the first one's solve without spilling.
 template <typename T, int BW, int NB>
-__global__ void __launch_bounds__(64) wave_ragged_kernel(const RaggedLines a, int first, int count) {
-    __shared__ __align__(16) T stage[Stage<T, WaveShape<NB>::E>::SIZE];
-    const int k = blockIdx.x;
-    if (k >= count) return;
-    wave_line<T, BW, NB>(RaggedSrc<T>{a}, first + k, stage);
+__device__ __forceinline__ void wave_unit(const RaggedLines &a, int first, int count, T *buf) {
+    constexpr int K = kWaveNBMax / NB;
+    constexpr bool PREFETCH = !(NB == 8 && BW == 2 && sizeof(T) == 8);
+    constexpr int E = WaveShape<NB>::E, NBB = WaveShape<NB>::NBB;
+    const gptr<const T> in = as_global(static_cast<const T *>(a.in));
+    const gptr<const int> order = as_global(a.order);
+    const gptr<const long long> offs = as_global(a.offsets);
+    auto line_of = [&](int q, long long &base, int &len) __attribute__((always_inline)) {
+        const int b = order[first + min(q, count - 1)];
+        base = offs[b];
+        len = static_cast<int>(offs[b + 1] - base);
+    };
+    auto solve = [&](long long base, int len, T (&raw)[NBB][E]) __attribute__((always_inline)) {
+        LineRef L;
+        L.in = static_cast<const T *>(a.in) + base;
+        L.out = static_cast<T *>(a.out) + base;
+        L.n = len;
+        L.p1 = a.p1;
+        L.p2 = a.p2;
+        L.invK = a.invK;
+        L.pow = a.pow;
+        wave_solve<T, BW, NB>(L, raw, buf);
+    };
+    T ra[NBB][E], rb[NBB][E];
+    long long b0, b1;
+    int n0, n1;
+    line_of(0, b0, n0);
+    wave_fetch<T, NB>(in + b0, n0, ra);
+    if constexpr (!PREFETCH) {
+        solve(b0, n0, ra);
+#pragma unroll
+        for (int q = 1; q < K; ++q) {
+            if (q < count) {
+                line_of(q, b0, n0);
+                wave_fetch<T, NB>(in + b0, n0, ra);
+                solve(b0, n0, ra);
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < K; q += 2) {
+        if (q + 1 < K) {
+            line_of(q + 1, b1, n1);
+            wave_fetch<T, NB>(in + b1, n1, rb);
+        }
+        if (q < count) solve(b0, n0, ra);
+        if (q + 1 < K) {
+            if (q + 2 < K) {
+                line_of(q + 2, b0, n0);
+                wave_fetch<T, NB>(in + b0, n0, ra);
+            }
+            if (q + 1 < count) solve(b1, n1, rb);
+        }
+    }
+}
+
+// Every ragged line of at most kWaveLineMax elements in one launch: one
+// wavefront per workgroup and one work unit per wavefront, the unit's length
+// class read from the unit table (a workgroup's registers are released when
+// its own unit is done, whatever the lengths of the lines beside it).
+template <typename T, int BW>
+__global__ void __launch_bounds__(64) wave_units_kernel(const RaggedLines a,
+                                                        const WaveUnit *__restrict__ units, int nunits) {
+    __shared__ __align__(16) T stage[Stage<T, WaveShape<kWaveNBMax>::E>::SIZE];
+    const int u = blockIdx.x;
+    if (u >= nunits) return;
+    const WaveUnit w = units[u];
+    switch (w.nb) {
+    case 1: wave_unit<T, BW, 1>(a, w.first, w.count, stage); break;
+    case 2: wave_unit<T, BW, 2>(a, w.first, w.count, stage); break;
+    case 4: wave_unit<T, BW, 4>(a, w.first, w.count, stage); break;
+    case 8: wave_unit<T, BW, 8>(a, w.first, w.count, stage); break;
+    default: wave_unit<T, BW, 16>(a, w.first, w.count, stage); break;
+    }
 }
 
 template <typename T, int BW, int NB>
@@ -369,17 +464,13 @@ __global__ void __launch_bounds__(64) wave_rows_kernel(const RowsInst *__restric
     wave_line<T, BW, NB>(RowsSrc<T>{inst, map}, first + k, stage);
 }
 
-template <typename T, int BW>
-hipError_t ragged_nb(int nb, const RaggedLines &a, int first, int count, hipStream_t s) {
-    const dim3 grid(count), block(64);
-    switch (nb) {
-    case 1: hipLaunchKernelGGL((wave_ragged_kernel<T, BW, 1>), grid, block, 0, s, a, first, count); break;
-    case 2: hipLaunchKernelGGL((wave_ragged_kernel<T, BW, 2>), grid, block, 0, s, a, first, count); break;
-    case 4: hipLaunchKernelGGL((wave_ragged_kernel<T, BW, 4>), grid, block, 0, s, a, first, count); break;
-    case 8: hipLaunchKernelGGL((wave_ragged_kernel<T, BW, 8>), grid, block, 0, s, a, first, count); break;
-    case 16: hipLaunchKernelGGL((wave_ragged_kernel<T, BW, 16>), grid, block, 0, s, a, first, count); break;
-    default: return hipErrorInvalidValue;
-    }
+template <typename T>
+hipError_t units_bw(int bw, const RaggedLines &a, const WaveUnit *units, int nunits, hipStream_t s) {
+    const dim3 grid(nunits), block(64);
+    if (bw == 2)
+        hipLaunchKernelGGL((wave_units_kernel<T, 2>), grid, block, 0, s, a, units, nunits);
+    else
+        hipLaunchKernelGGL((wave_units_kernel<T, 1>), grid, block, 0, s, a, units, nunits);
     return hipGetLastError();
 }
 
@@ -398,10 +489,6 @@ hipError_t rows_nb(int nb, const RowsInst *inst, const int *map, int first, int 
 }
 
 template <typename T>
-hipError_t ragged_bw(int bw, int nb, const RaggedLines &a, int first, int count, hipStream_t s) {
-    return bw == 2 ? ragged_nb<T, 2>(nb, a, first, count, s) : ragged_nb<T, 1>(nb, a, first, count, s);
-}
-template <typename T>
 hipError_t rows_bw(int bw, int nb, const RowsInst *inst, const int *map, int first, int count,
                    hipStream_t s) {
     return bw == 2 ? rows_nb<T, 2>(nb, inst, map, first, count, s)
@@ -410,13 +497,14 @@ hipError_t rows_bw(int bw, int nb, const RowsInst *inst, const int *map, int fir
 
 }  // namespace
 
-hipError_t launch_wave_ragged(int dtype, int bw, int nb, const RaggedLines &a, int first, int count,
-                              hipStream_t s) {
-    if (count <= 0) return hipSuccess;
+hipError_t launch_wave_units(int dtype, int bw, const RaggedLines &a, const WaveUnit *units, int nunits,
+                             hipStream_t s) {
+    if (nunits <= 0) return hipSuccess;
+    if (bw != 1 && bw != 2) return hipErrorInvalidValue;
     switch (dtype) {
-    case F64: return ragged_bw<double>(bw, nb, a, first, count, s);
-    case F32: return ragged_bw<float>(bw, nb, a, first, count, s);
-    case BF16: return ragged_bw<bf16>(bw, nb, a, first, count, s);
+    case F64: return units_bw<double>(bw, a, units, nunits, s);
+    case F32: return units_bw<float>(bw, a, units, nunits, s);
+    case BF16: return units_bw<bf16>(bw, a, units, nunits, s);
     default: return hipErrorInvalidValue;
     }
 }

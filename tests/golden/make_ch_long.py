@@ -1,18 +1,30 @@
 """Writes ch_long_parity.json: the oracle's Cahn-Hilliard state after many
-steps, sampled, for the long-horizon GPU parity test.
+steps, sampled, and the oracle's own rounding spread over the same run, for
+the long-horizon GPU parity test.
 
 Runs only the oracle (oracle.ch_run, the ADI step of Sec. 5.1 in double
 precision) from the seeded initial data of workloads.ch_initial (seed 2,
 0.1 U(-1, 1), the deep quench of Sec. 5.3) on the periodic square (0, 2 pi)^2
 with dt = 0.1 dx^2, D = 1, gamma = 0.01 and the start rule C^{-1} = C^0:
 
-* 1024 x 1024 for 1000 steps,
-* 4096 x 4096 for 20 steps.
+* 1024 x 1024 to 1000 steps (checkpoints 3, 10, 30, 100, 300, 1000),
+* 4096 x 4096 to 20 steps (checkpoints 2, 5, 10, 20).
 
-For each case it stores max |C| and the plain sum of the final C^n over the
-whole grid, every value of one row and one column, and 2048 seeded random
-points (seed 11).  One run takes about 9 minutes (1024^2) and 3 minutes
-(4096^2) single-threaded; the two cases run in separate processes.
+Rounding spread.  On a square grid (dx = dy) the x and y line operators of
+the scheme are the same matrix acting along the two axes, so they commute,
+and the 13-point biharmonic and 5-point Laplacian windows are symmetric under
+exchanging x and y (Sec. 5.1).  The exact run started from the transposed
+field C^0^T is therefore the transpose of the run from C^0.  In double
+precision the two runs round differently (rows and columns swap roles in
+every stencil sum and every line solve), so max |C_n - (C_n from C^0^T)^T|
+over the whole grid measures how far two equally valid double evaluations
+of the scheme drift apart after n steps.  The GPU test allows a stated small
+multiple of this spread.
+
+For each checkpoint the file stores the spread, max |C| and the plain sum of
+C^n, every value of one row and one column, and 2048 seeded random points
+(seed 11).  The four runs (two per grid) go to separate processes; the
+slowest (1024^2, 1000 steps) takes about 9 minutes single-threaded.
 
     python tests/golden/make_ch_long.py
 """
@@ -27,53 +39,82 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-CASES = ((1024, 1000), (4096, 20))
+CASES = ((1024, (3, 10, 30, 100, 300, 1000)), (4096, (2, 5, 10, 20)))
 NSAMPLE = 2048
 D, GAMMA = 1.0, 0.01
 
 
-def run_case(case):
+def run(args):
+    """The oracle run of one grid, from C^0 or from its transpose; returns
+    the state C^n at every checkpoint (transposed back for the second)."""
     import oracle
     from paper_1902_09931_amd import workloads as wl
 
-    n, steps = case
+    n, checkpoints, transposed = args
     c0 = wl.ch_initial(n, n, seed=2)
+    if transposed:
+        c0 = np.ascontiguousarray(c0.T)
     dx = 2 * math.pi / n
-    _, c = oracle.ch_run(c0, c0, steps, dx, dx, 0.1 * dx * dx, D, GAMMA)
-    rng = np.random.default_rng(11)
-    jj = rng.integers(0, n, NSAMPLE)
-    ii = rng.integers(0, n, NSAMPLE)
-    row, col = n // 3, (2 * n) // 5
-    return {
-        "n": n,
-        "steps": steps,
-        "dt": 0.1 * dx * dx,
-        "max_abs": float(np.abs(c).max()),
-        "sum": float(oracle.mass(c)),
-        "sum_abs_c0": float(np.abs(c0).sum()),
-        "row": row,
-        "row_values": c[row].tolist(),
-        "col": col,
-        "col_values": c[:, col].tolist(),
-        "points_j": jj.tolist(),
-        "points_i": ii.tolist(),
-        "points_values": c[jj, ii].tolist(),
-    }
+    cp, cc = c0.copy(), c0.copy()
+    done, states = 0, {}
+    for k in checkpoints:
+        cp, cc = oracle.ch_run(cp, cc, k - done, dx, dx, 0.1 * dx * dx, D, GAMMA)
+        done = k
+        states[k] = np.ascontiguousarray(cc.T) if transposed else cc.copy()
+    return states
 
 
 def main():
-    with ProcessPoolExecutor(len(CASES)) as ex:
-        results = list(ex.map(run_case, CASES))
+    import oracle
+    from paper_1902_09931_amd import workloads as wl
+
+    jobs = [(n, cps, t) for n, cps in CASES for t in (False, True)]
+    with ProcessPoolExecutor(len(jobs)) as ex:
+        results = list(ex.map(run, jobs))
+    cases = []
+    for ci, (n, cps) in enumerate(CASES):
+        ref, alt = results[2 * ci], results[2 * ci + 1]
+        c0 = wl.ch_initial(n, n, seed=2)
+        dx = 2 * math.pi / n
+        rng = np.random.default_rng(11)
+        jj = rng.integers(0, n, NSAMPLE)
+        ii = rng.integers(0, n, NSAMPLE)
+        row, col = n // 3, (2 * n) // 5
+        checks = []
+        for k in cps:
+            c = ref[k]
+            checks.append({
+                "steps": k,
+                "spread": float(np.abs(c - alt[k]).max()),
+                "max_abs": float(np.abs(c).max()),
+                "sum": float(oracle.mass(c)),
+                "row_values": c[row].tolist(),
+                "col_values": c[:, col].tolist(),
+                "points_values": c[jj, ii].tolist(),
+            })
+        cases.append({
+            "n": n,
+            "dt": 0.1 * dx * dx,
+            "max_abs_c0": float(np.abs(c0).max()),
+            "sum_abs_c0": float(np.abs(c0).sum()),
+            "row": row,
+            "col": col,
+            "points_j": jj.tolist(),
+            "points_i": ii.tolist(),
+            "checkpoints": checks,
+        })
     out = {
         "citation": "Sec. 5.1 (ADI scheme), Sec. 5.3 (random initial data); values from the oracle",
         "writer": "tests/golden/make_ch_long.py",
         "D": D,
         "gamma": GAMMA,
-        "cases": results,
+        "cases": cases,
     }
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "ch_long_parity.json")
     with open(path, "w") as f:
         json.dump(out, f)
+    for c in cases:
+        print(c["n"], [(k["steps"], k["spread"], k["max_abs"]) for k in c["checkpoints"]])
     print("wrote", path)
 
 

@@ -50,7 +50,14 @@ def rel_err(got, ref, mask=None):
 
 def stencil_bound(dt, s_abs, ref, taps, ncoe):
     """Stated forward bound of a stencil evaluated in float with storage
-    dtype dt: |err| <= (u_s + (K + ncoe + 3) u_32) sum_k |w_k||f|(|u_k|)
-    + u_s |out| (dot-product rounding, weight and point-function rounding in
-    float, then output rounding to the storage dtype)."""
-    return (U_STORE[dt] + (taps + ncoe + 3) * U32) * s_abs + U_STORE[dt] * np.abs(ref)
+    dtype dt, when the input is already in the storage dtype (both sides
+    read the same stored values, so input rounding has no part in it):
+
+        |err| <= (K + 2 ncoe + 2) u_32 sum_k |w_k| |f|(|u_k|) + u_s |out|
+
+    K float roundings of the dot product, one for each weight rounded to
+    float, 2 (ncoe - 1) for Horner's rule over ncoe coefficients plus one for
+    each coefficient rounded to float (the standard forward error analysis
+    of an inner product and of Horner's rule), and the final rounding of the
+    output to the storage dtype, u_s = 2^-24 (FP32) or 2^-8 (BF16)."""
+    return (taps + 2 * ncoe + 2) * U32 * s_abs + U_STORE[dt] * np.abs(ref)

@@ -158,10 +158,13 @@ def test_ch_1024_mass_and_parity():
 
 
 def test_ch_4096_one_step_parity():
+    """4096^2 FP64 in the layout the autotuner picks (the one the benchmark
+    times): two steps against the oracle to 1e-12 over the whole grid."""
     n = 4096
     c0 = wl.ch_initial(n, n, seed=2)
     g = Grid(c0)
     try:
+        b.mxs_autotune(g.plan)
         b.mxs_ch_step(g.plan, 2, True)
         torch.cuda.synchronize()
         gp, gc = g.state()
@@ -171,45 +174,118 @@ def test_ch_4096_one_step_parity():
     assert rel_err(gc, oc) <= 1e-12
 
 
+# Allowed multiple of the oracle's own rounding spread for the long FP64
+# runs (see the test below).
+SPREAD_MULTIPLE = 64
+
+
 @pytest.mark.parametrize("case", [0, 1], ids=["1024x1000", "4096x20"])
 def test_ch_long_horizon_parity_at_sampled_points(case):
-    """FP64 over many steps: 1024^2 after 1000 steps and 4096^2 after 20
-    steps.  The oracle's final state (tests/golden/ch_long_parity.json,
-    written by make_ch_long.py, which runs only the oracle) is compared on a
-    full row, a full column and 2048 seeded random points.  Over these
-    horizons the fastest linear growth, rate D / (4 gamma), amplifies
-    differences by less than 1.1, so GPU and oracle differ only by rounding,
-    which each step adds at the scale of the initial field and which
-    accumulates like a random walk (measured on 1024^2: 7.8e-15, 9.6e-15,
-    1.6e-14, 2.9e-14 after 3, 10, 30, 100 steps, while max |C| decays from
-    0.1 to 0.04): the bound is 1e-12 max|C^0| sqrt(steps).  The GPU's mass
-    equals the oracle's plain sum to 1e-12 of sum |C^0|."""
+    """FP64 over many steps: 1024^2 to 1000 steps and 4096^2 to 20 steps,
+    compared at every checkpoint of tests/golden/ch_long_parity.json (written
+    by make_ch_long.py from the oracle alone) on a full row, a full column
+    and 2048 seeded points.  The bound is a fixed multiple of the oracle's
+    own rounding spread at that checkpoint: the largest difference between
+    the oracle's run and its run from the transposed initial field
+    (transposed back), two equally valid double evaluations of the same
+    scheme on a square grid.  The GPU's mass equals the oracle's plain sum
+    to 1e-12 of sum |C^0|."""
     ref = golden("ch_long_parity.json")["cases"][case]
-    n, steps = ref["n"], ref["steps"]
+    n = ref["n"]
     c0 = wl.ch_initial(n, n, seed=2)
     g = Grid(c0)
+    rows = []
     try:
         assert g.dt == pytest.approx(ref["dt"], rel=1e-15)
-        b.mxs_ch_step(g.plan, steps, True)
-        m = b.mxs_ch_mass(g.plan)[0]
-        _, gc = g.state()
+        done = 0
+        for cp in ref["checkpoints"]:
+            b.mxs_ch_step(g.plan, cp["steps"] - done, True)
+            done = cp["steps"]
+            m = b.mxs_ch_mass(g.plan)[0]
+            _, gc = g.state()
+            diff = max(np.abs(gc[ref["row"]] - np.array(cp["row_values"])).max(),
+                       np.abs(gc[:, ref["col"]] - np.array(cp["col_values"])).max(),
+                       np.abs(gc[np.array(ref["points_j"]), np.array(ref["points_i"])] -
+                              np.array(cp["points_values"])).max())
+            rows.append((cp["steps"], diff, cp["spread"], abs(m - cp["sum"]) / ref["sum_abs_c0"]))
     finally:
         g.close()
-    tol = 1e-12 * np.abs(c0).max() * math.sqrt(steps)
-    assert np.abs(gc[ref["row"]] - np.array(ref["row_values"])).max() <= tol
-    assert np.abs(gc[:, ref["col"]] - np.array(ref["col_values"])).max() <= tol
-    pts = gc[np.array(ref["points_j"]), np.array(ref["points_i"])]
-    assert np.abs(pts - np.array(ref["points_values"])).max() <= tol
-    assert abs(np.abs(gc).max() - ref["max_abs"]) <= tol
-    assert abs(m - ref["sum"]) <= 1e-12 * ref["sum_abs_c0"]
+    for k, diff, spread, dm in rows:
+        print(f"n={n} step {k}: |GPU - oracle| {diff:.3e}, oracle spread {spread:.3e}, "
+              f"ratio {diff / spread:.2f}, mass difference {dm:.2e}")
+    for k, diff, spread, dm in rows:
+        assert diff <= SPREAD_MULTIPLE * spread, k
+        assert dm <= 1e-12, k
 
 
-@pytest.mark.parametrize("dt_name,bound", [("f32", 1e-4), ("bf16", 1e-1)])
-def test_ch_reduced_precision_error(dt_name, bound):
-    """FP32 / BF16 storage against the FP64 oracle from the same rounded
-    initial data, 200 steps on 128^2: relative error under the stated bound,
-    and the mass (summed in double) still conserved to the storage
-    precision."""
+def rhs_term_bound(cp, cc, dx, dy, dt):
+    """Per-point sum of the magnitudes of the terms of the right-hand side R
+    (Sec. 5.1): 2/3 |C^n - C^{n-1}| + a sum |w_b||Cbar| + 2/3 D dt sum
+    |w_l| (|C^n|^3 + |C^n|), with the 13-point biharmonic and 5-point
+    Laplacian windows; a float evaluation of R errs by at most a few float
+    roundings of this sum."""
+    d4 = np.array([1.0, 4.0, 6.0, 4.0, 1.0])
+    d2 = np.array([1.0, 2.0, 1.0])
+    wb = np.zeros((5, 5))
+    wb[2, :] += d4 / dx ** 4
+    wb[:, 2] += d4 / dy ** 4
+    wb[1:4, 1:4] += 2 * np.outer(d2, d2) / (dx * dx * dy * dy)
+    wl = np.zeros((3, 3))
+    wl[1, :] += d2 / dx ** 2
+    wl[:, 1] += d2 / dy ** 2
+    a = 2.0 / 3.0 * D * GAMMA * dt
+    cbar = np.abs(2 * cc - cp)
+    f = np.abs(cc) ** 3 + np.abs(cc)
+    return (2.0 / 3.0 * np.abs(cc - cp) + a * oracle.stencil2d(cbar, 2, 2, 2, 2, wb, True)
+            + 2.0 / 3.0 * D * dt * oracle.stencil2d(f, 1, 1, 1, 1, wl, True))
+
+
+# infinity norm of the inverse of either line operator I + beta d_xxxx: the
+# sum of |entries| of the inverse of the symbol 1 + 16 beta sin^4, below 1.15
+# for every beta and n (largest near beta = 300)
+LINV = 1.15
+
+
+@pytest.mark.parametrize("dt_name,shape", [("f32", (128, 128)), ("bf16", (128, 128)),
+                                           ("f32", (96, 160)), ("bf16", (96, 160))])
+def test_ch_reduced_precision_one_step_derived_bound(dt_name, shape):
+    """From the same stored state, one GPU step against one step of the
+    stored-precision oracle (double arithmetic, R and w rounded to float,
+    C^{n+1} to the storage dtype).  The two differ only by the float
+    arithmetic of the GPU's right-hand side (at most 32 float roundings of
+    the per-point term sum S, carried through two solves of infinity norm
+    below LINV), by a possible one-float-ulp difference in the rounding of
+    w, and by a possible one-ulp difference in the final rounding to the
+    storage dtype: |dC| <= 2 u_s |C| + LINV^2 (32 u_32 + 2 u_32) max S.
+    A kernel that evaluated R or stored w in BF16 would exceed it."""
+    ny, nx = shape
+    c0 = round_to(wl.ch_initial(ny, nx, seed=7), dt_name)
+    g = Grid(c0, dt_name)
+    try:
+        b.mxs_ch_step(g.plan, 5, True)
+        torch.cuda.synchronize()
+        cp, cc = g.state()
+        b.mxs_ch_step(g.plan, 1, False)
+        torch.cuda.synchronize()
+        _, got = g.state()
+    finally:
+        g.close()
+    ref = oracle.ch_step_stored(cp, cc, g.dx, g.dy, g.dt, dt_name)
+    s_max = rhs_term_bound(cp, cc, g.dx, g.dy, g.dt).max()
+    u32, us = 2.0 ** -24, {"f32": 2.0 ** -24, "bf16": 2.0 ** -8}[dt_name]
+    bound = 2 * us * np.abs(ref) + LINV ** 2 * (32 + 2) * u32 * s_max
+    err = np.abs(got - ref)
+    print(f"{dt_name} {shape}: max |dC| {err.max():.3e}, max of |dC| / bound {(err / bound).max():.3f}, "
+          f"cells differing by more than the arithmetic term {np.mean(err > LINV ** 2 * 34 * u32 * s_max):.2e}")
+    assert np.all(err <= bound)
+
+
+@pytest.mark.parametrize("dt_name", ["f32", "bf16"])
+def test_ch_reduced_precision_error(dt_name):
+    """FP32 / BF16 storage against the FP64 oracle and the stored-precision
+    oracle from the same rounded initial data, 200 steps on 128^2: the error
+    against each, and the mass (summed in double) still conserved to the
+    storage precision."""
     n = 128
     c0 = round_to(wl.ch_initial(n, n, seed=7), dt_name)
     g = Grid(c0, dt_name)
@@ -222,10 +298,13 @@ def test_ch_reduced_precision_error(dt_name, bound):
     finally:
         g.close()
     _, oc = oracle.ch_run(c0, c0, 200, g.dx, g.dy, g.dt, D, GAMMA)
-    err = rel_err(gc, oc)
-    print(f"{dt_name}: relative error after 200 steps {err:.3e}, mass drift "
-          f"{abs(m - m0) / np.abs(c0).sum():.3e}")
-    assert err <= bound
+    _, sc = oracle.ch_run_stored(c0, c0, 200, g.dx, g.dy, g.dt, dt_name, D, GAMMA)
+    err, err_s, err_os = rel_err(gc, oc), rel_err(gc, sc), rel_err(sc, oc)
+    drift = abs(m - m0) / np.abs(c0).sum()
+    print(f"{dt_name}: after 200 steps, GPU vs FP64 oracle {err:.3e}, GPU vs stored-precision "
+          f"oracle {err_s:.3e}, stored-precision oracle vs FP64 oracle {err_os:.3e}; mass drift "
+          f"{drift:.3e}")
+    assert err <= {"f32": 1e-4, "bf16": 1e-1}[dt_name]
 
 
 def test_ch_ensemble_matches_single_grids_and_oracle():
@@ -285,24 +364,32 @@ def test_ch_argument_errors():
 
 def test_autotune_keeps_the_state_and_parity():
     """Tuning times whole steps without advancing: the step count and both
-    time levels are unchanged, and the run continues to the oracle's answer."""
+    time levels are unchanged, the graphs captured before tuning are not
+    replayed after it (the tables they point at are rebuilt), and graph
+    steps after tuning match eager steps of an untuned twin bit for bit and
+    the oracle to 1e-12."""
     c0 = wl.ch_initial(72, 96, seed=21)
-    g = Grid(c0)
+    g, twin = Grid(c0), Grid(c0)
     try:
-        b.mxs_ch_step(g.plan, 2, True)
+        b.mxs_ch_step(g.plan, 4, True)       # captures graphs of every rotation
+        b.mxs_ch_step(twin.plan, 4, False)
         torch.cuda.synchronize()
         before = g.state()
         b.mxs_autotune(g.plan)
         assert "rhs_rows=" in b.mxs_plan_info(g.plan)
-        assert b.mxs_ch_steps_taken(g.plan) == 2
+        assert b.mxs_ch_steps_taken(g.plan) == 4
         after = g.state()
         assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
-        b.mxs_ch_step(g.plan, 3, True)
-        torch.cuda.synchronize()
+        for k in range(4):
+            b.mxs_ch_step(g.plan, 1, True)
+            b.mxs_ch_step(twin.plan, 1, False)
+            torch.cuda.synchronize()
+            assert np.array_equal(g.state()[1], twin.state()[1]), k
         _, gc = g.state()
     finally:
         g.close()
-    _, oc = oracle.ch_run(c0, c0, 5, g.dx, g.dy, g.dt, D, GAMMA)
+        twin.close()
+    _, oc = oracle.ch_run(c0, c0, 8, g.dx, g.dy, g.dt, D, GAMMA)
     assert rel_err(gc, oc) <= 1e-12
 
 
@@ -338,6 +425,10 @@ def test_ch_ensemble_64_reduced_precision_against_oracle(dt_name, bound20, bound
     def oracle_run(k, nsteps):
         return oracle.ch_run(c0s[k], c0s[k], nsteps, dxs[k], dxs[k], dts[k], D, GAMMA)[1]
 
+    def stored_run(k, nsteps):
+        return oracle.ch_run_stored(c0s[k], c0s[k], nsteps, dxs[k], dxs[k], dts[k], dt_name,
+                                    D, GAMMA)[1]
+
     try:
         m0 = b.mxs_ch_mass(plan, len(sizes))
         b.mxs_ch_step(plan, 20, True)
@@ -346,6 +437,8 @@ def test_ch_ensemble_64_reduced_precision_against_oracle(dt_name, bound20, bound
         got20 = {k: state(k) for k in pick20}
         refs = dict(zip(pick20, pool.map(lambda k: oracle_run(k, 20), pick20)))
         err20 = {k: rel_err(got20[k], refs[k]) for k in pick20}
+        srefs = dict(zip(pick20, pool.map(lambda k: stored_run(k, 20), pick20)))
+        serr20 = {k: rel_err(got20[k], srefs[k]) for k in pick20}
         b.mxs_ch_step(plan, 480, True)
         torch.cuda.synchronize()
         m = b.mxs_ch_mass(plan, len(sizes))
@@ -353,12 +446,15 @@ def test_ch_ensemble_64_reduced_precision_against_oracle(dt_name, bound20, bound
         got500 = {k: state(k) for k in pick500}
         refs = dict(zip(pick500, pool.map(lambda k: oracle_run(k, 500), pick500)))
         err500 = {k: rel_err(got500[k], refs[k]) for k in pick500}
+        srefs = dict(zip(pick500, pool.map(lambda k: stored_run(k, 500), pick500)))
+        serr500 = {k: rel_err(got500[k], srefs[k]) for k in pick500}
     finally:
         b.mxs_destroy(plan)
         pool.shutdown()
     drift = max(abs(m[k] - m0[k]) / np.abs(c0s[k]).sum() for k in range(len(sizes)))
     print(f"{dt_name}: max relative error after 20 steps {max(err20.values()):.3e} "
           f"({len(err20)} instances), after 500 steps {max(err500.values()):.3e} "
-          f"(8 smallest), max mass drift {drift:.3e}")
+          f"(8 smallest), max mass drift {drift:.3e}; against the stored-precision oracle "
+          f"{max(serr20.values()):.3e} (20 steps), {max(serr500.values()):.3e} (500 steps)")
     assert max(err20.values()) <= bound20
     assert max(err500.values()) <= bound500

@@ -65,3 +65,16 @@ def test_no_flat_or_scratch_memory_instructions(code_objects):
                              capture_output=True, text=True).stdout
         hits = bad.findall(asm)
         assert not hits, (obj.name, hits[:5])
+
+
+def test_no_scalar_memory_writes(code_objects):
+    """Global memory is written only through vector memory instructions: no
+    scalar-cache store, atomic, write-back or discard appears in any kernel
+    (kernels that write a table from one lane must still use vector stores)."""
+    objdump = _tool("llvm-objdump")
+    bad = re.compile(r"\bs_(store|buffer_store|atomic|buffer_atomic|dcache_wb|dcache_discard)\w*")
+    for obj in code_objects:
+        asm = subprocess.run([objdump, "-d", str(obj)], check=True,
+                             capture_output=True, text=True).stdout
+        hits = bad.findall(asm)
+        assert not hits, (obj.name, hits[:5])

@@ -134,3 +134,59 @@ def test_rectangular_grids_solve_each_direction(shape):
         v = (-2.0 / 3.0 * (an - anm1) - aa * sx ** 2 * abar) / (1 + aa * sx ** 2)
         anm1, an = an, abar + v
     assert np.abs(cc - an * mode).max() < 1e-14
+
+
+# --- the stored-precision form (reduced-precision reading) -------------------
+
+def test_storage_rounding_is_nearest_even():
+    """round_storage: float rounding equals NumPy's float32 cast; bfloat16
+    rounding equals torch's float32 -> bfloat16 conversion (round to nearest
+    even) on float values, and takes the documented ties: halfway between
+    two bfloat16 values goes to the even one, just above halfway goes up."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(20000) * np.exp(rng.uniform(-30, 30, 20000))
+    assert np.array_equal(oracle.round_storage(x, "f32"), x.astype(np.float32).astype(np.float64))
+    xf = x.astype(np.float32).astype(np.float64)
+    ref = torch.from_numpy(xf.astype(np.float32)).to(torch.bfloat16).double().numpy()
+    assert np.array_equal(oracle.round_storage(xf, "bf16"), ref)
+    ulp = 2.0 ** -7
+    ties = np.array([1 + ulp / 2, 1 + 3 * ulp / 2, -(1 + ulp / 2), 1 + ulp / 2 + 2.0 ** -40, 0.0])
+    assert list(oracle.round_storage(ties, "bf16")) == [1.0, 1 + 2 * ulp, -1.0, 1 + ulp, 0.0]
+
+
+def test_stored_step_rounds_the_stored_quantities():
+    """The stored-precision step: storage "f64" is the plain step bit for
+    bit; with "f32" or "bf16" every value of C^{n+1} is a value of that dtype,
+    and after one step the result lies within the rounding of its storage
+    (plus the float rounding of R and w carried through the two solves) of
+    the double-precision step."""
+    ny, nx = 40, 48
+    dx, dy = 2 * math.pi / nx, 2 * math.pi / ny
+    dt = 0.1 * dx * dx
+    c0 = 0.1 * np.random.default_rng(8).uniform(-1, 1, (ny, nx))
+    plain = oracle.ch_step(c0, c0, dx, dy, dt)
+    assert np.array_equal(oracle.ch_step_stored(c0, c0, dx, dy, dt, "f64"), plain)
+    for storage, u in (("f32", 2.0 ** -24), ("bf16", 2.0 ** -8)):
+        cs = oracle.round_storage(c0, storage)
+        ref = oracle.ch_step(cs, cs, dx, dy, dt)
+        got = oracle.ch_step_stored(cs, cs, dx, dy, dt, storage)
+        assert np.array_equal(oracle.round_storage(got, storage), got)
+        # C^{n+1} rounded once (u |C|), w and R rounded to float and carried
+        # through the two solves (each inverse has infinity norm about 1.1:
+        # the sum of |entries| of the inverse of the symbol 1 + 16 beta sin^4)
+        assert np.all(np.abs(got - ref) <= u * np.abs(ref) + 64 * 2.0 ** -24 * np.abs(c0).max())
+        if storage == "bf16":
+            assert np.abs(got - ref).max() > 2.0 ** -24 * np.abs(ref).max()
+
+
+def test_stored_run_continues_the_stored_step():
+    ny, nx = 24, 32
+    dx, dy = 2 * math.pi / nx, 2 * math.pi / ny
+    dt = 0.1 * dx * dx
+    c0 = oracle.round_storage(0.1 * np.random.default_rng(9).uniform(-1, 1, (ny, nx)), "bf16")
+    cp, cc = c0, c0
+    for _ in range(5):
+        cp, cc = cc, oracle.ch_step_stored(cp, cc, dx, dy, dt, "bf16")
+    rp, rc = oracle.ch_run_stored(c0, c0, 5, dx, dy, dt, "bf16")
+    assert np.array_equal(rc, cc) and np.array_equal(rp, cp)

@@ -273,3 +273,59 @@ def test_ragged_first_derivative_symbol_per_signal():
         seg = out[offs[b]:offs[b + 1]]
         assert np.all(np.isnan(seg[:2])) and np.all(np.isnan(seg[-2:]))
         assert not np.any(np.isnan(seg[2:-2]))
+
+
+# --- the point-sampled definition and the workload tables -------------------
+
+@pytest.mark.parametrize("periodic", [True, False])
+@pytest.mark.parametrize("ext,coe", [((2, 2, 0, 0), None), ((0, 0, 1, 3), None),
+                                     ((2, 1, 2, 1), None), ((1, 1, 1, 1), (0.0, -1.0, 0.0, 1.0))])
+def test_stencil2d_at_equals_the_whole_grid_definition(ext, coe, periodic):
+    """orc_stencil2d_at (the reference of the sampled full-size parity tests)
+    returns, at random, corner and border points, exactly the values of
+    orc_stencil2d over the whole grid, and marks as unwritten exactly the
+    cells that the whole-grid call leaves untouched."""
+    L, R, T, B = ext
+    rng = np.random.default_rng(31)
+    ny, nx = 41, 57
+    u = rng.uniform(-1, 1, (ny, nx))
+    w = rng.uniform(-1, 1, (L + R + 1) * (T + B + 1))
+    full = np.full_like(u, np.nan)
+    oracle.stencil2d(u, L, R, T, B, w, periodic, coe=coe, out=full)
+    js = np.concatenate([rng.integers(0, ny, 400), [0, 0, ny - 1, ny - 1],
+                         np.arange(ny), np.full(nx, T), np.full(nx, ny - 1 - B)])
+    is_ = np.concatenate([rng.integers(0, nx, 400), [0, nx - 1, 0, nx - 1],
+                          np.full(ny, L), np.arange(nx), np.arange(nx)])
+    vals, written = oracle.stencil2d_at(u, L, R, T, B, w, periodic, js, is_, coe=coe)
+    expect = full[js, is_]
+    assert np.array_equal(written, ~np.isnan(expect))
+    assert np.array_equal(vals[written], expect[written])
+    assert periodic or not written.all()
+
+
+def test_workload_weight_tables_are_the_derived_stencils():
+    """The coefficient tables the workloads feed to the library are the
+    moment-system weights: D2_4TH the 5-point 4th-order second derivative,
+    D1_4TH the 5-point 4th-order first derivative, D2_2ND the 3-point
+    second difference, LAPLACE_3X3 the x and y second differences summed
+    in a 3x3 window (dx = dy), CROSS_XXYY the outer product of two second
+    differences (Fig. 1)."""
+    d2_4 = [float(v) for v in fd_weights(2, range(-2, 3))]
+    d1_4 = [float(v) for v in fd_weights(1, range(-2, 3))]
+    d2_2 = [float(v) for v in fd_weights(2, range(-1, 2))]
+    assert list(wl.D2_4TH) == d2_4
+    assert list(wl.D1_4TH) == d1_4
+    assert list(wl.D2_2ND) == d2_2
+    lap = np.zeros((3, 3))
+    lap[1, :] += d2_2
+    lap[:, 1] += d2_2
+    assert np.array_equal(np.array(wl.LAPLACE_3X3), lap)
+    assert np.array_equal(np.array(wl.CROSS_XXYY), np.outer(d2_2, d2_2))
+    # the 4th-order label: the second-derivative table is exact on monomials
+    # up to degree p + m - 1 = 5 ...
+    h = np.arange(-2, 3, dtype=float)
+    for q in range(6):
+        target = 2.0 if q == 2 else 0.0
+        assert abs(np.dot(d2_4, h ** q) - target) < 1e-12, q
+    # ... and not on x^6 (so it is 4th order, not higher)
+    assert abs(np.dot(d2_4, h ** 6)) > 1.0

@@ -222,3 +222,69 @@ def test_row_kernels(monkeypatch, kernel, nx):
     torch.cuda.synchronize()
     b.mxs_destroy(p)
     check(to_host(dx), oracle.cyclic_solve_grid(oracle.circulant_bands(PENTA_SMALL), 1, r), "f64")
+
+
+def test_ragged_solve_is_one_launch_and_graph_capturable():
+    """The ragged solve of lines up to 4096 elements is one launch (every
+    length class in one grid of work units), and it can be captured into a
+    HIP graph: every replay, with eager work and synchronisation between
+    replays, equals the eager result bit for bit."""
+    lengths, offs = wl.ragged_lengths(nbatch=3000, seed=13)
+    r = np.random.default_rng(14).uniform(-1, 1, int(offs[-1]))
+    drhs = to_device(r, "f64")
+    x_eager = torch.empty_like(drhs)
+    x_graph = torch.full_like(drhs, float("nan"))
+    pe = b.mxs_create_cyclic_solve(1, TRI, b.MXS_LINES_RAGGED, 0, 0, 0, offs, b.MXS_F64, drhs, x_eager)
+    pg = b.mxs_create_cyclic_solve(1, TRI, b.MXS_LINES_RAGGED, 0, 0, 0, offs, b.MXS_F64, drhs, x_graph)
+    try:
+        assert "launches=1 " in b.mxs_plan_info(pg)
+        b.mxs_compute(pe)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            b.mxs_compute(pg)          # warm-up outside the capture
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            b.mxs_compute(pg)
+        for k in range(4):
+            x_graph.fill_(float("nan"))
+            g.replay()
+            torch.cuda.synchronize()
+            _ = torch.ones(1000, device="cuda").sum().item()
+            assert torch.equal(x_graph, x_eager), k
+    finally:
+        b.mxs_destroy(pe)
+        b.mxs_destroy(pg)
+    ref = oracle.cyclic_solve_batch(oracle.circulant_bands(TRI), offs, r)
+    check(x_eager.cpu().numpy(), ref, "f64")
+
+
+@pytest.mark.parametrize("geometry", ["rows", "cols"])
+def test_grid_swap_then_set_io(geometry):
+    """Swap exchanges rhs and x without touching device memory (the tables of
+    both orientations exist from the start); set_io rebinds after a swap."""
+    ny, nx = 40, 50
+    r = np.random.default_rng(19).uniform(-1, 1, (ny, nx))
+    a = to_device(r, "f64")
+    c = torch.empty_like(a)
+    geo = b.MXS_LINES_ROWS if geometry == "rows" else b.MXS_LINES_COLS
+    axis = 1 if geometry == "rows" else 0
+    bands = oracle.circulant_bands(PENTA_SMALL)
+    p = b.mxs_create_cyclic_solve(2, PENTA_SMALL, geo, nx, ny, nx, None, b.MXS_F64, a, c)
+    try:
+        b.mxs_compute(p)           # c = A^-1 a
+        b.mxs_swap(p)
+        b.mxs_compute(p)           # a = A^-1 c
+        torch.cuda.synchronize()
+        ref2 = oracle.cyclic_solve_grid(bands, axis, oracle.cyclic_solve_grid(bands, axis, r))
+        check(to_host(a), ref2, "f64")
+        d = torch.empty_like(a)
+        b.mxs_set_io(p, c, d)      # d = A^-1 c
+        b.mxs_compute(p)
+        torch.cuda.synchronize()
+        check(to_host(d), oracle.cyclic_solve_grid(bands, axis, to_host(c)), "f64")
+    finally:
+        b.mxs_destroy(p)
