@@ -38,6 +38,15 @@ TRAFFIC_SOURCES = ["paper_1902_09931_amd/csrc/stencil2d.hip", "paper_1902_09931_
 # tile layouts (rows, order, threads, streaming stores) used by the counter runs
 PROFILE_LAYOUTS = "x=4,1,256,1;y=16,1,256,1;xy=16,1,256,1;fun=16,1,256,1"
 METRIC = "stencil Gpoints/s + % HBM peak; CH ADI steps/s (FP64 vs FP32/batched)"
+# The paper's own serial-versus-GPU figures (Sec. 5.4), for context only: a
+# different machine and a different program (its whole ADI Cahn-Hilliard code).
+PAPER_SPEEDUP = {
+    "gpu_vs_serial_cpu": "O(10) for all reasonable grid resolutions, up to 40x for large N",
+    "workload": "whole 2D ADI Cahn-Hilliard program (stencils and periodic pentadiagonal solves), "
+                "N x N periodic grid to T = 10, FP64",
+    "gpu": "NVIDIA Titan X Pascal",
+    "cpu": "Intel i7-6850K (6 cores, 3.6 GHz), serial code",
+}
 
 
 def log(msg):
@@ -416,6 +425,101 @@ def np_ascontig(a):
     return np.ascontiguousarray(a)
 
 
+def host_threads():
+    return max(1, min(len(os.sched_getaffinity(0)), 16))
+
+
+def timed(fn):
+    t0 = time.perf_counter()
+    fn()
+    return time.perf_counter() - t0
+
+
+def threaded(jobs):
+    """Run independent oracle calls (closures) on one thread each; the oracle
+    releases the GIL inside its C code.  Returns the wall time."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(len(jobs)) as pool:
+        t0 = time.perf_counter()
+        list(pool.map(lambda f: f(), jobs))
+        return time.perf_counter() - t0
+
+
+def split_batch(offs, parts):
+    """Split a ragged batch (offsets) into `parts` contiguous signal ranges of
+    about equal point counts: list of (values slice start, stop, local offsets)."""
+    import numpy as np
+    total = int(offs[-1])
+    cuts = [int(np.searchsorted(offs, total * k / parts)) for k in range(parts)] + [len(offs) - 1]
+    out = []
+    for a, z in zip(cuts[:-1], cuts[1:]):
+        if z > a:
+            out.append((int(offs[a]), int(offs[z]), np.ascontiguousarray(offs[a:z + 1] - offs[a])))
+    return out
+
+
+def cpu_baseline_sections(wl):
+    """The oracle on every other workload of the bench, on the host cores:
+    single-threaded (the paper's serial baseline) and with independent
+    signals, lines or grids spread over the host threads.  Each figure is
+    per pass or per step of the whole workload; CH steps are timed over one
+    step and stated as extrapolated."""
+    import math
+    import numpy as np
+    import oracle
+    nt = host_threads()
+    out = {"host_cpu": cpu_model(), "host_threads_used": nt}
+    lengths, offs = wl.ragged_lengths()
+    total = int(offs[-1])
+    v = wl.ragged_values(total)
+    parts = split_batch(offs, nt)
+    d1 = list(wl.D1_4TH)
+    t1 = timed(lambda: oracle.stencil1d_batch(v, offs, 2, 2, d1, True))
+    tn = threaded([lambda a=a, z=z, o=o: oracle.stencil1d_batch(v[a:z], o, 2, 2, d1, True)
+                   for a, z, o in parts])
+    out["ragged1d_stencil"] = {"s_per_pass_1_thread": t1, "s_per_pass_all_threads": tn,
+                               "gpoints_per_s_1_thread": total / t1 / 1e9,
+                               "gpoints_per_s_all_threads": total / tn / 1e9,
+                               "sample": f"the whole batch: {len(lengths)} signals, {total} points"}
+    r = np.random.default_rng(5).uniform(-1, 1, total)
+    bands = oracle.circulant_bands([2.5, -1.0])
+    t1 = timed(lambda: oracle.cyclic_solve_batch(bands, offs, r))
+    tn = threaded([lambda a=a, z=z, o=o: oracle.cyclic_solve_batch(bands, o, r[a:z])
+                   for a, z, o in parts])
+    out["cyclic_tri_batch"] = {"s_per_pass_1_thread": t1, "s_per_pass_all_threads": tn,
+                               "gpoints_per_s_1_thread": total / t1 / 1e9,
+                               "gpoints_per_s_all_threads": total / tn / 1e9,
+                               "sample": f"the whole batch: {len(lengths)} lines, {total} points"}
+    n = 4096
+    c0 = wl.ch_initial(n, n, seed=2)
+    dx = 2 * math.pi / n
+    t1 = timed(lambda: oracle.ch_run(c0, c0, 1, dx, dx, 0.1 * dx * dx, 1.0, 0.01))
+    out["ch_adi_4096_f64"] = {"s_per_step_1_thread": t1, "steps_per_s_1_thread": 1.0 / t1,
+                              "sample": "one step of the 4096^2 FP64 ADI step (extrapolated)"}
+    del c0
+    sizes = wl.ensemble_sizes()
+    c0s = wl.ensemble_initial(sizes)
+    jobs = []
+    for nn, c in zip(sizes, c0s):
+        d = 2 * math.pi / nn
+        jobs.append(lambda c=c, d=d: oracle.ch_run(c, c, 1, d, d, 0.1 * d * d, 1.0, 0.01))
+    t1 = timed(lambda: [f() for f in jobs])
+    # instances dealt to threads largest first, so the threads finish together
+    order = sorted(range(len(sizes)), key=lambda k: -sizes[k])
+    groups = [[] for _ in range(nt)]
+    load = [0] * nt
+    for k in order:
+        g = load.index(min(load))
+        groups[g].append(jobs[k])
+        load[g] += sizes[k] ** 2
+    tn = threaded([lambda grp=grp: [f() for f in grp] for grp in groups if grp])
+    out["ch_ensemble_64_f64"] = {"s_per_step_1_thread": t1, "s_per_step_all_threads": tn,
+                                 "steps_per_s_1_thread": 1.0 / t1, "steps_per_s_all_threads": 1.0 / tn,
+                                 "sample": f"one FP64 step of all {len(sizes)} grids "
+                                           f"({sum(s * s for s in sizes)} points; extrapolated)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -424,6 +528,8 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-cpu-sections", action="store_true",
+                    help="time the oracle on the stencil set and the 1024^2 CH step only")
     ap.add_argument("--sections-only", action="store_true",
                     help="skip the headline stencil set (for profiling the sections)")
     ap.add_argument("--sections", default="f32,ragged,tri,ch,ensemble,copy",
@@ -523,6 +629,33 @@ def main():
         result["cpu_baseline"] = cpu_baseline(wl, n, rows=min(n, 3072))
         extra["cpu_baseline_all_cores"] = cpu_baseline_threads(wl, n, rows=min(n, 3072))
         extra["cpu_baseline_ch_1024"] = cpu_baseline_ch(1024)
+        if not args.no_cpu_sections:
+            cs = cpu_baseline_sections(wl)
+            extra["cpu_baseline_sections"] = cs
+            # GPU speed-up over the oracle, beside each GPU figure
+            for dt in ("f64", "f32"):
+                for key, cpu in (("ragged1d_stencil", cs["ragged1d_stencil"]),
+                                 ("cyclic_tri_batch", cs["cyclic_tri_batch"])):
+                    sec = extra.get(f"{key}_{dt}")
+                    if sec:
+                        sec["oracle_s_per_pass_1_thread"] = cpu["s_per_pass_1_thread"]
+                        sec["oracle_s_per_pass_all_threads"] = cpu["s_per_pass_all_threads"]
+                        sec["speedup_vs_oracle_1_thread"] = cpu["s_per_pass_1_thread"] / sec["s_per_pass"]
+                        sec["speedup_vs_oracle_all_threads"] = (cpu["s_per_pass_all_threads"] /
+                                                                sec["s_per_pass"])
+            ch = extra.get("ch_adi_4096_f64")
+            if ch:
+                ch["oracle_steps_per_s_1_thread"] = cs["ch_adi_4096_f64"]["steps_per_s_1_thread"]
+                ch["speedup_vs_oracle_1_thread"] = ch["steps_per_s"] / ch["oracle_steps_per_s_1_thread"]
+            ens = extra.get("ch_ensemble_64")
+            if ens:
+                ce = cs["ch_ensemble_64_f64"]
+                ens["oracle_f64_steps_per_s_1_thread"] = ce["steps_per_s_1_thread"]
+                ens["oracle_f64_steps_per_s_all_threads"] = ce["steps_per_s_all_threads"]
+                for name in ("f32", "bf16", "f64"):
+                    ens[f"ensemble_{name}_speedup_vs_oracle_all_threads"] = (
+                        ens[f"ensemble_{name}_steps_per_s"] / ce["steps_per_s_all_threads"])
+        extra["paper_speedup"] = PAPER_SPEEDUP
     if args.sections_only:     # no headline was measured: report the sections alone
         result = {"sections_only": True, "extra": extra}
     print(json.dumps(result), flush=True)
