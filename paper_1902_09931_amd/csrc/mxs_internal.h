@@ -241,6 +241,9 @@ struct Stencil2DArgs {
     int order;              // tile order: 0 = each XCD a contiguous run of row chunks
                             // of one strip; 1 = row-major sweep (strips fastest)
     int nt_store;           // 1: non-temporal output stores
+    int block_rows;         // 0: streaming form; 8 or 16: block form reading
+                            // that many input rows per workgroup at once
+                            // (rows = block_rows - NWY + 1 output rows)
 };
 
 // Vectors per thread in one tile of the batched 1D stencil (a tile is
@@ -273,7 +276,9 @@ hipError_t launch_stencil2d(int dtype, int nwx, int nwy, const Stencil2DArgs &a,
                             int threads, hipStream_t s);
 hipError_t launch_stencil1d(int dtype, int nwx, const Stencil1DArgs &a, int threads,
                             int grid, hipStream_t s);
-size_t stencil2d_lds_bytes(int dtype, int nwx, int nwy, int threads);
+size_t stencil2d_lds_bytes(int dtype, int nwx, int nwy, int threads, int block_rows);
+// Whether the block form is compiled for this padded window and row count.
+bool stencil2d_block_ok(int nwx, int nwy, int block_rows);
 size_t stencil1d_lds_bytes(int dtype, int nwx, int threads, int max_sig);
 
 }  // namespace mxs

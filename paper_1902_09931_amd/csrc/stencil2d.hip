@@ -355,6 +355,188 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
     }
 }
 
+// Block form (windows of 3 or 5 rows): a workgroup requests all GIN input
+// rows of its chunk at once, GIN - NWY + 1 output rows, stages them in LDS
+// with their x halo (NWX > 1) and computes every output row of the chunk;
+// there is no streaming loop, so every load of the workgroup is in flight
+// together, as in a plain copy.  Neighbouring chunks both read the NWY - 1
+// rows they share; with chunks of one strip dispatched close together the
+// second read is served by L2.  Rows and columns outside a non-periodic grid
+// are read from clamped addresses: they only meet outputs that are not
+// written (or padded taps of weight zero).
+template <typename T, int NWX, int NWY, int GIN, bool CLEAN>
+__device__ __forceinline__ void block_body(const Stencil2DArgs &a, int strip, int chunk, unsigned char *smem) {
+    using A = typename St<T>::acc;
+    constexpr int V = St<T>::V;
+    constexpr int PAD = halo_pad<NWX, V>();
+    constexpr int XW = V + NWX - 1;
+    constexpr int ROWS = GIN - NWY + 1;
+    constexpr int HPT = (GIN * 2 * PAD + 63) / 64;
+    A *lds = reinterpret_cast<A *>(smem);
+    const gptr<const T> in = as_global(static_cast<const T *>(a.in));
+    const gptr<T> out = as_global(static_cast<T *>(a.out));
+    const A *__restrict__ w = static_cast<const A *>(a.wts);
+    const A *coe = coe_of<A>(a);
+    const int nt = blockDim.x;
+    const int t = threadIdx.x;
+    const int W = nt * V;
+    const int rowlen = PAD + W + PAD;
+    const long long i0 = static_cast<long long>(strip) * W;
+    const int j0 = chunk * ROWS;
+    const int H = min(ROWS, a.ny - j0);
+    const long long ib = i0 + static_cast<long long>(t) * V;
+    const bool periodic = a.periodic != 0;
+
+    // grid row of input row u
+    auto in_row = [&](int u) __attribute__((always_inline)) {
+        long long r = static_cast<long long>(j0) - a.T + u;
+        if (periodic) return wrap_fast(r, a.ny);
+        return r < 0 ? 0LL : (r >= a.ny ? static_cast<long long>(a.ny) - 1 : r);
+    };
+    A xin[GIN][V];
+#pragma unroll
+    for (int u = 0; u < GIN; ++u) {
+        const gptr<const T> rowp = in + in_row(u) * a.ld;
+        if (CLEAN) {
+            load_vec<T>(rowp + ib, xin[u]);
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                long long c = ib + v;
+                c = periodic ? wrap_fast(c, a.nx) : (c >= a.nx ? a.nx - 1 : c);
+                xin[u][v] = to_acc<T>(gld<T>(rowp, c));
+            }
+        }
+    }
+    A hv[HPT > 0 ? HPT : 1];
+    const int hcount = GIN * 2 * PAD;
+#pragma unroll
+    for (int q = 0; q < HPT; ++q) {
+        const int h = min(t + q * nt, hcount - 1);
+        const int u = h / (2 * PAD);
+        const int hh = h - u * 2 * PAD;
+        long long c = hh < PAD ? i0 - PAD + hh : i0 + W + (hh - PAD);
+        c = periodic ? wrap_fast(c, a.nx) : (c < 0 ? 0 : (c >= a.nx ? a.nx - 1 : c));
+        hv[q] = to_acc<T>(gld<T>(in + in_row(u) * a.ld, c));
+    }
+    if (a.ncoe) {
+        // Horner's rule, coefficient loop outside (one uniform load per
+        // coefficient), the same operations per element as point_fun
+        const A top = coe[a.ncoe - 1];
+        A f[GIN][V], hf[HPT > 0 ? HPT : 1];
+#pragma unroll
+        for (int u = 0; u < GIN; ++u)
+#pragma unroll
+            for (int v = 0; v < V; ++v) f[u][v] = top;
+#pragma unroll
+        for (int q = 0; q < HPT; ++q) hf[q] = top;
+        for (int m = a.ncoe - 2; m >= 0; --m) {
+            const A cm = coe[m];
+#pragma unroll
+            for (int u = 0; u < GIN; ++u)
+#pragma unroll
+                for (int v = 0; v < V; ++v) f[u][v] = f[u][v] * xin[u][v] + cm;
+#pragma unroll
+            for (int q = 0; q < HPT; ++q) hf[q] = hf[q] * hv[q] + cm;
+        }
+#pragma unroll
+        for (int u = 0; u < GIN; ++u)
+#pragma unroll
+            for (int v = 0; v < V; ++v) xin[u][v] = f[u][v];
+#pragma unroll
+        for (int q = 0; q < HPT; ++q) hv[q] = hf[q];
+    }
+    if constexpr (NWX > 1) {
+#pragma unroll
+        for (int u = 0; u < GIN; ++u) {
+            A *dst = lds + u * rowlen + PAD + t * V;
+#pragma unroll
+            for (int v = 0; v < V; ++v) dst[v] = xin[u][v];
+        }
+#pragma unroll
+        for (int q = 0; q < HPT; ++q) {
+            const int h = t + q * nt;
+            if (h < hcount) {
+                const int u = h / (2 * PAD);
+                const int hh = h - u * 2 * PAD;
+                lds[u * rowlen + (hh < PAD ? hh : W + hh)] = hv[q];
+            }
+        }
+        __syncthreads();
+    }
+    const bool store_vec_ok = a.vec_ok && ib + V <= a.nx &&
+                              (periodic || (ib >= a.L && ib + V - 1 <= a.nx - 1 - a.R));
+#pragma unroll
+    for (int k = 0; k < ROWS; ++k) {
+        A acc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = A(0);
+#pragma unroll
+        for (int q = 0; q < NWY; ++q) {
+            if constexpr (NWX > 1) {
+                A x[XW];
+                const A *lp = lds + (k + q) * rowlen + PAD + t * V - a.L;
+#pragma unroll
+                for (int m = 0; m < XW; ++m) x[m] = lp[m];
+#pragma unroll
+                for (int p = 0; p < NWX; ++p) {
+                    const A wt = w[q * NWX + p];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) acc[v] = fma(wt, x[v + p], acc[v]);
+                }
+            } else {
+                const A wt = w[q];
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[v] = fma(wt, xin[k + q][v], acc[v]);
+            }
+        }
+        const int j = j0 + k;
+        if (k >= H || (!periodic && (j < a.T || j > a.ny - 1 - a.B))) continue;
+        const gptr<T> rowp = out + static_cast<long long>(j) * a.ld;
+        if (CLEAN && store_vec_ok) {
+            if (a.nt_store) store_vec_nt<T>(rowp + ib, acc);
+            else store_vec<T>(rowp + ib, acc);
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const long long c = ib + v;
+                if (c < a.nx && (periodic || (c >= a.L && c <= a.nx - 1 - a.R)))
+                    gst<T>(rowp, c, from_acc<T>(acc[v]));
+            }
+        }
+    }
+}
+
+template <typename T, int NWX, int NWY, int GIN>
+__global__ void __launch_bounds__(256) stencil2d_block_kernel(const Stencil2DArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int strip, chunk;
+    if (a.order == 0) {
+        const int tile = xcd_tile(blockIdx.x, gridDim.x);
+        strip = tile / a.nchunks;
+        chunk = tile - strip * a.nchunks;
+    } else {
+        chunk = blockIdx.x / a.nstrips;
+        strip = blockIdx.x - chunk * a.nstrips;
+    }
+    const long long W = static_cast<long long>(blockDim.x) * St<T>::V;
+    // a strip whose vectors all lie inside the grid, aligned: vector loads only
+    if (a.vec_ok && (strip + 1) * W <= a.nx)
+        block_body<T, NWX, NWY, GIN, true>(a, strip, chunk, smem_raw);
+    else
+        block_body<T, NWX, NWY, GIN, false>(a, strip, chunk, smem_raw);
+}
+
+template <typename T, int NWX, int NWY, int GIN>
+hipError_t launch_block(const Stencil2DArgs &a, int threads, hipStream_t s) {
+    using A = typename St<T>::acc;
+    constexpr int V = St<T>::V;
+    const size_t lds = NWX > 1 ? static_cast<size_t>(GIN) * (2 * halo_pad<NWX, V>() + threads * V) * sizeof(A) : 0;
+    const int grid = a.nstrips * a.nchunks;
+    hipLaunchKernelGGL((stencil2d_block_kernel<T, NWX, NWY, GIN>), dim3(grid), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
 template <typename T, int NWX, int NWY>
 hipError_t launch_one(const Stencil2DArgs &a, int threads, hipStream_t s) {
     using A = typename St<T>::acc;
@@ -368,7 +550,19 @@ hipError_t launch_one(const Stencil2DArgs &a, int threads, hipStream_t s) {
 }
 
 template <typename T>
+hipError_t dispatch_block(int nwx, int nwy, const Stencil2DArgs &a, int threads, hipStream_t s) {
+#define MXS_BCASE(X, Y, G) \
+    if (nwx == X && nwy == Y && a.block_rows == G) return launch_block<T, X, Y, G>(a, threads, s);
+    MXS_BCASE(1, 3, 8) MXS_BCASE(1, 3, 16) MXS_BCASE(1, 5, 8) MXS_BCASE(1, 5, 16)
+    MXS_BCASE(3, 3, 8) MXS_BCASE(3, 3, 16) MXS_BCASE(3, 5, 8) MXS_BCASE(3, 5, 16)
+    MXS_BCASE(5, 3, 8) MXS_BCASE(5, 3, 16) MXS_BCASE(5, 5, 8) MXS_BCASE(5, 5, 16)
+#undef MXS_BCASE
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
 hipError_t dispatch(int nwx, int nwy, const Stencil2DArgs &a, int threads, hipStream_t s) {
+    if (a.block_rows) return dispatch_block<T>(nwx, nwy, a, threads, s);
 #define MXS_CASE(X, Y) \
     if (nwx == X && nwy == Y) return launch_one<T, X, Y>(a, threads, s);
     MXS_CASE(1, 1) MXS_CASE(3, 1) MXS_CASE(5, 1) MXS_CASE(9, 1) MXS_CASE(17, 1)
@@ -391,12 +585,16 @@ int bucket_width(int taps) {
     return 0;
 }
 
-size_t stencil2d_lds_bytes(int dtype, int nwx, int nwy, int threads) {
+bool stencil2d_block_ok(int nwx, int nwy, int block_rows) {
+    return (nwx == 1 || nwx == 3 || nwx == 5) && (nwy == 3 || nwy == 5) && (block_rows == 8 || block_rows == 16);
+}
+
+size_t stencil2d_lds_bytes(int dtype, int nwx, int nwy, int threads, int block_rows) {
     if (nwx <= 1) return 0;
     const int V = dtype == F64 ? St<double>::V : dtype == F32 ? St<float>::V : St<bf16>::V;
     const int acc = dtype == F64 ? 8 : 4;
     const int pad = ((nwx - 1 + V - 1) / V) * V;
-    const int g = 4;
+    const int g = block_rows ? block_rows : 4;
     (void)nwy;
     return static_cast<size_t>(g) * (2 * pad + threads * V) * acc;
 }

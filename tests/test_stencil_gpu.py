@@ -284,7 +284,10 @@ def test_stencil1d_full_batch(dt):
 # a spread of shapes plus every layout the autotuner picked for the 8192^2
 # FP64 and FP32 stencil sets on the GPU
 LAYOUTS = ["2,1,256,1", "4,0,256,0", "8,1,128,1", "16,0,128,0", "64,1,256,1", "128,0,256,1",
-           "3,1,64,0", "4,1,256,1", "16,1,256,1", "128,1,256,1", "8,0,256,1", "64,0,256,1"]
+           "3,1,64,0", "4,1,256,1", "16,1,256,1", "128,1,256,1", "8,0,256,1", "64,0,256,1",
+           # block form (fifth field: input rows per workgroup; windows of 3 or 5
+           # rows only, others keep their default layout)
+           "1,1,256,1,8", "1,0,128,0,8", "1,1,128,1,16", "1,0,256,0,16", "1,1,64,1,16"]
 LAYOUT_WINDOWS = [("X", (2, 2, 0, 0), None), ("Y", (0, 0, 2, 1), None), ("XY", (1, 2, 2, 1), None),
                   ("XY", (1, 1, 1, 1), wl.CUBIC_MINUS_LINEAR)]
 
@@ -304,6 +307,31 @@ def test_every_layout_keeps_parity(monkeypatch, layout, dt, direction, ext, coe)
     for periodic in (True, False):
         got = run_2d(u, direction, periodic, ext, w, coe, dt)
         check_against_oracle(u, got, direction, periodic, ext, w, coe, dt)
+
+
+BLOCK_WINDOWS = [("Y", (0, 0, 1, 1)), ("Y", (0, 0, 2, 2)), ("Y", (0, 0, 3, 0)), ("XY", (1, 1, 1, 1)),
+                 ("XY", (2, 1, 0, 2)), ("XY", (2, 2, 2, 2)), ("XY", (0, 1, 1, 0))]
+
+
+@pytest.mark.parametrize("layout", ["1,1,64,1,8", "1,0,128,0,16"])
+@pytest.mark.parametrize("shape", [(5, 9), (8, 70), (37, 45), (257, 129), (23, 1030)])
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+def test_block_form_small_and_ragged_grids(monkeypatch, layout, shape, dt):
+    """The block form on grids with fewer rows than one chunk, ragged last
+    chunks and strips, unaligned pitches and padded windows, periodic and
+    not, with and without the point function."""
+    monkeypatch.setenv("MXS_STENCIL_TILE", layout)
+    rng = np.random.default_rng(hash((shape, layout, dt)) % (1 << 32))
+    u = rng.uniform(-1, 1, shape)
+    for k, (direction, ext) in enumerate(BLOCK_WINDOWS):
+        L, R, T, B = ext
+        if T + B >= shape[0] or L + R >= shape[1]:
+            continue
+        w = rng.uniform(-1, 1, (T + B + 1) * (L + R + 1))
+        coe = wl.CUBIC_MINUS_LINEAR if k % 2 else None
+        for periodic in (True, False):
+            got = run_2d(u, direction, periodic, ext, w, coe, dt, ld_pad=k % 3)
+            check_against_oracle(u, got, direction, periodic, ext, w, coe, dt)
 
 
 def test_autotune_keeps_parity_and_reports_layout():
