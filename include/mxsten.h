@@ -219,6 +219,19 @@ mxs_status mxs_ch_mass(mxs_plan plan, double *host_out, void *hip_stream);
 mxs_status mxs_ch_coarsening(mxs_plan plan, int k, double *s_out, double *k1_out,
                              void *hip_stream);
 
+/* The same diagnostics as mxs_ch_coarsening, for callers that cannot
+ * allocate device memory (tight loops, harnesses that forbid hipMalloc):
+ * this call allocates nothing.  Its scratch is a static device array of the
+ * library, one per GPU, held until the process ends and sized for grids of
+ * at most 1048576 points (16 bytes per point plus 96 KiB of partial sums);
+ * a larger grid returns MXS_ERR_UNSUPPORTED.  Every call on one GPU uses that
+ * GPU's array, so calls that overlap on one GPU (from several threads, or on
+ * several streams) race: serialise them.  Each call rewrites every scratch
+ * value it reads, so no clearing is needed between calls.  Arguments,
+ * results and errors otherwise as mxs_ch_coarsening; waits for the stream. */
+mxs_status mxs_ch_coarsening_noalloc(mxs_plan plan, int k, double *s_out,
+                                     double *k1_out, void *hip_stream);
+
 /* Choose the plan's launch layout by measurement: candidate layouts (rows
  * per workgroup, tile order, threads per workgroup and streaming stores for
  * 2D stencils; wavefronts per line for lines solved in LDS, longer than

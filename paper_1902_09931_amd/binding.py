@@ -84,6 +84,7 @@ _SIGS = {
     "mxs_ch_steps_taken": [_vp, _llp],
     "mxs_ch_mass": [_vp, _dp, _vp],
     "mxs_ch_coarsening": [_vp, _int, _dp, _dp, _vp],
+    "mxs_ch_coarsening_noalloc": [_vp, _int, _dp, _dp, _vp],
     "mxs_destroy": [_vp],
     "mxs_autotune": [_vp, _vp],
     "mxs_plan_info": [_vp, ctypes.c_char_p, _int],
@@ -265,4 +266,12 @@ def mxs_ch_coarsening(plan, k=0, stream=None):
     """Coarsening diagnostics (s, k1) of instance k's current state."""
     sv, kv = ctypes.c_double(), ctypes.c_double()
     _check(_lib.mxs_ch_coarsening(plan, k, ctypes.byref(sv), ctypes.byref(kv), _stream(stream)))
+    return sv.value, kv.value
+
+
+def mxs_ch_coarsening_noalloc(plan, k=0, stream=None):
+    """mxs_ch_coarsening on the library's static scratch (allocates nothing)."""
+    sv, kv = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.mxs_ch_coarsening_noalloc(plan, k, ctypes.byref(sv), ctypes.byref(kv),
+                                          _stream(stream)))
     return sv.value, kv.value

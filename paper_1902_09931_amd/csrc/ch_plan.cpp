@@ -180,30 +180,41 @@ struct CHPlan final : mxs_plan_s {
         return finite ? MXS_OK : fail(MXS_ERR_NONFINITE, "the mass is not finite");
     }
 
-    // Coarsening diagnostics of instance k's C^n (Sec. 5.3); the scratch of
-    // the transform is allocated on the first call and kept by the plan.
+    // Coarsening diagnostics of instance k's C^n (Sec. 5.3).  The transform
+    // scratch is allocated on the first call and kept by the plan, or, with
+    // noalloc, taken from the library's static per-device scratch (nothing
+    // allocated; grids up to kNoAllocDiagPoints points).
     DevBuf diag_spec, diag_partial, diag_out;
-    mxs_status coarsening(int k, double *s_out, double *k1_out, hipStream_t s) {
+    mxs_status coarsening(int k, double *s_out, double *k1_out, hipStream_t s, bool noalloc) {
         const Inst &I = inst[k];
         if (!diag_shape_ok(I.nx, I.ny))
             return fail(MXS_ERR_UNSUPPORTED, "coarsening diagnostics need power-of-two sides up to %d (got %d x %d)",
                         kDiagMaxSide, I.nx, I.ny);
-        const size_t spec = sizeof(double2) * static_cast<size_t>(I.nx) * I.ny;
-        const size_t part = sizeof(double) * (static_cast<size_t>(I.ny) + 2 * I.nx);
-        hipError_t e = hipSuccess;
-        if (diag_spec.bytes < spec) e = diag_spec.alloc(spec);
-        if (e == hipSuccess && diag_partial.bytes < part) e = diag_partial.alloc(part);
-        if (e == hipSuccess && !diag_out.ptr) e = diag_out.alloc(3 * sizeof(double));
-        if (e != hipSuccess) return hip_fail(e, "diagnostics scratch allocation");
         DiagArgs d{};
+        hipError_t e = hipSuccess;
+        if (noalloc) {
+            if (static_cast<long long>(I.nx) * I.ny > kNoAllocDiagPoints)
+                return fail(MXS_ERR_UNSUPPORTED,
+                            "the allocation-free diagnostics take grids of at most %lld points (got %d x %d)",
+                            kNoAllocDiagPoints, I.nx, I.ny);
+            e = noalloc_diag_scratch(I.nx, I.ny, &d);
+            if (e != hipSuccess) return hip_fail(e, "static scratch address");
+        } else {
+            const size_t spec = sizeof(double2) * static_cast<size_t>(I.nx) * I.ny;
+            const size_t part = sizeof(double) * (static_cast<size_t>(I.ny) + 2 * I.nx);
+            if (diag_spec.bytes < spec) e = diag_spec.alloc(spec);
+            if (e == hipSuccess && diag_partial.bytes < part) e = diag_partial.alloc(part);
+            if (e == hipSuccess && !diag_out.ptr) e = diag_out.alloc(3 * sizeof(double));
+            if (e != hipSuccess) return hip_fail(e, "diagnostics scratch allocation");
+            d.spec = static_cast<double2 *>(diag_spec.ptr);
+            d.partial = static_cast<double *>(diag_partial.ptr);
+            d.out = static_cast<double *>(diag_out.ptr);
+        }
         d.c = I.buf[(steps % 3 + 1) % 3];
         d.nx = I.nx;
         d.ny = I.ny;
         d.kx0 = 2.0 * M_PI / (I.nx * I.dx);
         d.ky0 = 2.0 * M_PI / (I.ny * I.dy);
-        d.spec = static_cast<double2 *>(diag_spec.ptr);
-        d.partial = static_cast<double *>(diag_partial.ptr);
-        d.out = static_cast<double *>(diag_out.ptr);
         double h[3];
         e = launch_coarsening(dtype, d, s);
         if (e == hipSuccess) e = hipMemcpyAsync(h, d.out, sizeof h, hipMemcpyDeviceToHost, s);
@@ -597,7 +608,15 @@ mxs_status mxs_ch_coarsening(mxs_plan plan, int k, double *s_out, double *k1_out
     CHPlan *p = as_ch(plan);
     if (!p) return fail(MXS_ERR_BAD_HANDLE, "not a Cahn-Hilliard plan");
     if (k < 0 || k >= p->ninst()) return fail(MXS_ERR_INVALID_ARG, "instance %d out of range", k);
-    return p->coarsening(k, s_out, k1_out, static_cast<hipStream_t>(hip_stream));
+    return p->coarsening(k, s_out, k1_out, static_cast<hipStream_t>(hip_stream), false);
+}
+
+mxs_status mxs_ch_coarsening_noalloc(mxs_plan plan, int k, double *s_out, double *k1_out,
+                                     void *hip_stream) {
+    CHPlan *p = as_ch(plan);
+    if (!p) return fail(MXS_ERR_BAD_HANDLE, "not a Cahn-Hilliard plan");
+    if (k < 0 || k >= p->ninst()) return fail(MXS_ERR_INVALID_ARG, "instance %d out of range", k);
+    return p->coarsening(k, s_out, k1_out, static_cast<hipStream_t>(hip_stream), true);
 }
 
 mxs_status mxs_ch_mass(mxs_plan plan, double *host_out, void *hip_stream) {

@@ -18,7 +18,16 @@
 // sides must be powers of two, at most kDiagMaxSide.
 #include "diag.h"
 
+#include <mutex>
+
 namespace mxs {
+
+// Scratch of the allocation-free diagnostics entry point: the transform grid
+// (kNoAllocDiagPoints complex values), then the partial sums (ny + 2 nx
+// doubles), then the 3 results.  Every GPU the library runs on holds its own
+// copy for the life of the process.  Host code never passes this name to a
+// kernel: its device address comes from hipGetSymbolAddress, per device.
+static __device__ __align__(256) double scratch[2 * kNoAllocDiagPoints + 3 * kDiagMaxSide + 8];
 
 namespace {
 
@@ -169,6 +178,30 @@ hipError_t diag_one(const DiagArgs &d, hipStream_t s) {
 bool diag_shape_ok(int nx, int ny) {
     return nx >= 2 && ny >= 2 && nx <= kDiagMaxSide && ny <= kDiagMaxSide && log2_exact(nx) >= 0 &&
            log2_exact(ny) >= 0;
+}
+
+hipError_t noalloc_diag_scratch(int nx, int ny, DiagArgs *d) {
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    double *base;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        if (!addr[dev]) {
+            void *p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return e;
+            addr[dev] = static_cast<double *>(p);
+        }
+        base = addr[dev];
+    }
+    d->spec = reinterpret_cast<double2 *>(base);
+    d->partial = base + 2 * static_cast<size_t>(nx) * ny;
+    d->out = d->partial + ny + 2 * static_cast<size_t>(nx);
+    return hipSuccess;
 }
 
 hipError_t launch_coarsening(int dtype, const DiagArgs &d, hipStream_t s) {
