@@ -59,12 +59,15 @@ def lib():
         L.orc_ch_run_stored.argtypes = [_ll, _ll, _dbl, _dbl, _dbl, _dbl, _dbl, _int, _int, _ll,
                                         _f64p, _f64p]
         L.orc_round_storage.argtypes = [_f64p, _f64p, _ll, _int]
+        L.orc_weno_adv.argtypes = [_f64p, _f64p, _f64p, _f64p, _ll, _ll, _ll, _dbl, _dbl]
+        L.orc_weno_derivatives.argtypes = [_f64p, _f64p, _f64p, _f64p, _f64p, _ll, _ll, _ll,
+                                           _dbl, _dbl]
         L.orc_sum.argtypes = [_f64p, _ll]
         L.orc_sum.restype = _dbl
         for name in ("orc_stencil2d", "orc_stencil2d_at", "orc_stencil1d_batch",
                      "orc_cyclic_solve_batch", "orc_cyclic_solve_grid", "orc_ch_step",
                      "orc_ch_run", "orc_ch_step_stored", "orc_ch_run_stored",
-                     "orc_round_storage"):
+                     "orc_round_storage", "orc_weno_adv", "orc_weno_derivatives"):
             getattr(L, name).restype = _int
         _lib = L
     return _lib
@@ -239,3 +242,24 @@ def mass(x):
     """Grid mass sum_ij C_ij with compensated summation."""
     x = _f64(x).ravel()
     return float(lib().orc_sum(x, x.size))
+
+
+def weno_adv(phi, u, v, dx, dy):
+    """The WENO advection variant of Sec. 4.3 on a periodic grid shaped (ny,
+    nx): out = u phi_x + v phi_y with fifth-order Hamilton-Jacobi WENO
+    derivatives upwinded by the sign of each velocity."""
+    phi, u, v = _f64(phi), _f64(u), _f64(v)
+    ny, nx = phi.shape
+    out = np.zeros_like(phi)
+    _check(lib().orc_weno_adv(phi, u, v, out, nx, ny, nx, dx, dy), "weno_adv")
+    return out
+
+
+def weno_derivatives(phi, u, v, dx, dy):
+    """The upwind WENO derivatives (phi_x, phi_y) the advection term uses."""
+    phi, u, v = _f64(phi), _f64(u), _f64(v)
+    ny, nx = phi.shape
+    px, py = np.zeros_like(phi), np.zeros_like(phi)
+    _check(lib().orc_weno_derivatives(phi, u, v, px, py, nx, ny, nx, dx, dy),
+           "weno_derivatives")
+    return px, py
