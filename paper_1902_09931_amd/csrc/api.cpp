@@ -159,9 +159,10 @@ struct Stencil2DPlan final : mxs_plan_s {
     // rows: output rows per workgroup (streaming form), or ignored in the
     // block form, which reads block rows per workgroup (block_rows - nwy + 1
     // output rows).
-    void set_layout(int rows, int order, int nthreads, int nt, int block = 0) {
+    void set_layout(int rows, int order, int nthreads, int nt, int block = 0, int xs = 0) {
         threads = nthreads;
         a.block_rows = block;
+        a.xshuffle = block ? xs : 0;
         if (block) rows = block - nwy + 1;
         a.rows = rows;
         a.order = order;
@@ -183,12 +184,13 @@ struct Stencil2DPlan final : mxs_plan_s {
         set_layout(rows, 1, 256, 1);
         // explicit override "rows,order,threads,nt[,block]" for experiments
         if (const char *env = getenv("MXS_STENCIL_TILE")) {
-            int r = 0, o = 0, t = 0, nt = 1, blk = 0;
-            const int k = sscanf(env, "%d,%d,%d,%d,%d", &r, &o, &t, &nt, &blk);
+            int r = 0, o = 0, t = 0, nt = 1, blk = 0, xs = 0;
+            const int k = sscanf(env, "%d,%d,%d,%d,%d,%d", &r, &o, &t, &nt, &blk, &xs);
             if (k >= 3 && r > 0 && (o == 0 || o == 1) && (t == 64 || t == 128 || t == 256) &&
                 (blk == 0 || stencil2d_block_ok(nwx, nwy, blk)) &&
-                stencil2d_lds_bytes(dtype, nwx, nwy, t, blk) <= static_cast<size_t>(device_lds_limit()))
-                set_layout(r, o, t, nt != 0, blk);
+                (xs == 0 || stencil2d_xshuffle_ok(dtype, nwx, nwy, a.L, a.R, blk)) &&
+                stencil2d_lds_bytes(dtype, nwx, nwy, t, blk, xs) <= static_cast<size_t>(device_lds_limit()))
+                set_layout(r, o, t, nt != 0, blk, xs);
         }
     }
 
@@ -201,8 +203,9 @@ struct Stencil2DPlan final : mxs_plan_s {
 
     mxs_status autotune(hipStream_t s) override;
     void info(char *buf, int len) const override {
-        snprintf(buf, len, "stencil2d dtype=%d window=%dx%d rows=%d order=%d threads=%d nt_store=%d block=%d grid=%d",
-                 dtype, nwx, nwy, a.rows, a.order, threads, a.nt_store, a.block_rows, a.nstrips * a.nchunks);
+        snprintf(buf, len, "stencil2d dtype=%d window=%dx%d rows=%d order=%d threads=%d nt_store=%d block=%d xshuffle=%d grid=%d",
+                 dtype, nwx, nwy, a.rows, a.order, threads, a.nt_store, a.block_rows, a.xshuffle,
+                 a.nstrips * a.nchunks);
     }
 
     mxs_status set_io(const void *in, void *out) {
@@ -263,7 +266,7 @@ struct Stencil1DPlan final : mxs_plan_s {
 
 namespace {
 struct TunedLayout {
-    int rows, order, threads, nt, block;
+    int rows, order, threads, nt, block, xs;
 };
 std::mutex g_tune_mu;
 std::map<std::string, TunedLayout> g_tuned;
@@ -274,11 +277,12 @@ mxs_status Stencil2DPlan::autotune(hipStream_t s) {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_tuned.find(key());
         if (it != g_tuned.end()) {
-            set_layout(it->second.rows, it->second.order, it->second.threads, it->second.nt, it->second.block);
+            set_layout(it->second.rows, it->second.order, it->second.threads, it->second.nt, it->second.block,
+                       it->second.xs);
             return MXS_OK;
         }
     }
-    const TunedLayout start{a.rows, a.order, threads, a.nt_store, a.block_rows};
+    const TunedLayout start{a.rows, a.order, threads, a.nt_store, a.block_rows, a.xshuffle};
     // every candidate is timed in two passes and keeps its faster time (the
     // best layouts differ by a few percent, about the spread of one timing)
     struct Cand {
@@ -290,29 +294,45 @@ mxs_status Stencil2DPlan::autotune(hipStream_t s) {
     for (int rows : {2, 4, 8, 16, 32, 64, 128}) {
         if (rows > 2 * a.ny && rows > 2) continue;
         for (int nthreads : {256, 128}) {
-            if (stencil2d_lds_bytes(dtype, nwx, nwy, nthreads, 0) > lds_limit) continue;
+            if (stencil2d_lds_bytes(dtype, nwx, nwy, nthreads, 0, 0) > lds_limit) continue;
             for (int order : {1, 0})
-                for (int nt : {1, 0}) cands.push_back({TunedLayout{rows, order, nthreads, nt, 0}, 1e30});
+                for (int nt : {1, 0}) cands.push_back({TunedLayout{rows, order, nthreads, nt, 0, 0}, 1e30});
         }
     }
     // block form: all input rows of a chunk requested at once
-    for (int block : {8, 16}) {
+    for (int block : {8, 12, 16}) {
         if (!stencil2d_block_ok(nwx, nwy, block) || block - nwy + 1 > 2 * a.ny) continue;
-        for (int nthreads : {256, 128}) {
-            if (stencil2d_lds_bytes(dtype, nwx, nwy, nthreads, block) > lds_limit) continue;
-            for (int order : {1, 0})
-                for (int nt : {1, 0})
-                    cands.push_back({TunedLayout{block - nwy + 1, order, nthreads, nt, block}, 1e30});
+        for (int xs : {0, 1}) {
+            if (xs && !stencil2d_xshuffle_ok(dtype, nwx, nwy, a.L, a.R, block)) continue;
+            for (int nthreads : {256, 128}) {
+                if (stencil2d_lds_bytes(dtype, nwx, nwy, nthreads, block, xs) > lds_limit) continue;
+                for (int order : {1, 0})
+                    for (int nt : {1, 0})
+                        cands.push_back({TunedLayout{block - nwy + 1, order, nthreads, nt, block, xs}, 1e30});
+            }
         }
     }
     if (cands.empty()) return MXS_OK;
+    // Grids whose input and output are between half and four times the
+    // memory-side cache are timed with that cache flushed before each
+    // launch: back to back, such a grid would find part of its data still
+    // cached, which a caller streaming over many grids does not.  Smaller
+    // grids stay cached in real use too; larger ones (four times the cache
+    // or more) evict their own data before they come back to it.
+    const size_t data = 2 * grid_bytes(a.nx, a.ny, a.ld, dtype);
+    DevBuf flush;
+    if (data > kMallBytes / 2 && data < 4 * kMallBytes && flush.alloc(kFlushBytes) != hipSuccess) {
+        (void)hipGetLastError();
+        flush.bytes = 0;
+    }
     for (int pass = 0; pass < 2; ++pass) {
         for (Cand &c : cands) {
-            set_layout(c.l.rows, c.l.order, c.l.threads, c.l.nt, c.l.block);
-            const double t = time_launches(
-                [&] { return launch_stencil2d(dtype, nwx, nwy, a, threads, s); }, s, 2, 5);
+            set_layout(c.l.rows, c.l.order, c.l.threads, c.l.nt, c.l.block, c.l.xs);
+            auto launch = [&] { return launch_stencil2d(dtype, nwx, nwy, a, threads, s); };
+            const double t = flush.bytes ? time_launches_cold(launch, s, 1, 5, flush.ptr, flush.bytes)
+                                         : time_launches(launch, s, 2, 5);
             if (t < 0) {
-                set_layout(start.rows, start.order, start.threads, start.nt, start.block);
+                set_layout(start.rows, start.order, start.threads, start.nt, start.block, start.xs);
                 return hip_fail(hipGetLastError(), "autotune launch");
             }
             c.t = std::min(c.t, t);
@@ -325,7 +345,7 @@ mxs_status Stencil2DPlan::autotune(hipStream_t s) {
             best_t = c.t;
             best = c.l;
         }
-    set_layout(best.rows, best.order, best.threads, best.nt, best.block);
+    set_layout(best.rows, best.order, best.threads, best.nt, best.block, best.xs);
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tuned[key()] = best;
     return MXS_OK;
@@ -396,7 +416,7 @@ mxs_status mxs_create_2d(const mxs_stencil2d_desc *d, mxs_plan *plan) {
         return st;
     }
     p->default_layout();
-    if (stencil2d_lds_bytes(p->dtype, nwx, nwy, p->threads, 0) > static_cast<size_t>(device_lds_limit())) {
+    if (stencil2d_lds_bytes(p->dtype, nwx, nwy, p->threads, 0, 0) > static_cast<size_t>(device_lds_limit())) {
         delete p;
         return fail(MXS_ERR_UNSUPPORTED, "window needs more LDS than the device offers");
     }

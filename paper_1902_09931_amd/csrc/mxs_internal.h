@@ -244,6 +244,8 @@ struct Stencil2DArgs {
     int block_rows;         // 0: streaming form; 8 or 16: block form reading
                             // that many input rows per workgroup at once
                             // (rows = block_rows - NWY + 1 output rows)
+    int xshuffle;           // block form, centred windows: x neighbours by
+                            // lane shifts instead of an LDS row
 };
 
 // Vectors per thread in one tile of the batched 1D stencil (a tile is
@@ -276,9 +278,15 @@ hipError_t launch_stencil2d(int dtype, int nwx, int nwy, const Stencil2DArgs &a,
                             int threads, hipStream_t s);
 hipError_t launch_stencil1d(int dtype, int nwx, const Stencil1DArgs &a, int threads,
                             int grid, hipStream_t s);
-size_t stencil2d_lds_bytes(int dtype, int nwx, int nwy, int threads, int block_rows);
+size_t stencil2d_lds_bytes(int dtype, int nwx, int nwy, int threads, int block_rows, int xshuffle);
+// Read `bytes` (a multiple of 16) of a device buffer once, so that the
+// memory-side cache holds none of the data timed next.
+hipError_t launch_cache_flush(void *buf, size_t bytes, hipStream_t s);
 // Whether the block form is compiled for this padded window and row count.
 bool stencil2d_block_ok(int nwx, int nwy, int block_rows);
+// Whether the block form can take x neighbours from neighbouring lanes
+// (centred windows of padded width nwx, at most one vector on each side).
+bool stencil2d_xshuffle_ok(int dtype, int nwx, int nwy, int left, int right, int block_rows);
 size_t stencil1d_lds_bytes(int dtype, int nwx, int threads, int max_sig);
 
 }  // namespace mxs

@@ -6,7 +6,7 @@
 
 #include <stddef.h>
 
-enum PlanKind { KIND_STENCIL2D = 1, KIND_STENCIL1D = 2, KIND_SOLVE = 3, KIND_CH = 4 };
+enum PlanKind { KIND_STENCIL2D = 1, KIND_STENCIL1D = 2, KIND_SOLVE = 3, KIND_CH = 4, KIND_WENO = 5 };
 
 struct mxs_plan_s {
     int kind;
@@ -37,6 +37,11 @@ struct DevBuf {
     hipError_t alloc(size_t n);
     hipError_t upload(const void *src, size_t n);
 };
+
+// Memory-side cache (MALL) of the device, and the buffer written to flush it
+// when layouts are timed on cold caches.
+constexpr size_t kMallBytes = size_t(256) << 20;
+constexpr size_t kFlushBytes = size_t(512) << 20;
 
 mxs_status fail(mxs_status st, const char *fmt, ...);
 mxs_status hip_fail(hipError_t e, const char *what);
@@ -72,6 +77,36 @@ template <class F> double time_launches(F &&fn, hipStream_t s, int warm, int rep
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return r;
+}
+
+// Average time of single launches of fn, each started with the memory-side
+// cache (MALL) holding other data: before every timed launch the stream
+// reads flush (flush_bytes, larger than that cache; reads leave no dirty
+// lines to be written back during the timed launch).  For plans whose
+// data exceed the cache, so that each candidate layout meets the cold
+// caches that back-to-back launches over many buffers meet.
+template <class F>
+double time_launches_cold(F &&fn, hipStream_t s, int warm, int reps, void *flush, size_t flush_bytes) {
+    for (int i = 0; i < warm; ++i)
+        if (fn() != hipSuccess) return -1.0;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.0;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.0;
+    }
+    double total = 0.0;
+    bool ok = true;
+    for (int i = 0; i < reps && ok; ++i) {
+        float ms = 0;
+        ok = launch_cache_flush(flush, flush_bytes, s) == hipSuccess && hipEventRecord(e0, s) == hipSuccess &&
+             fn() == hipSuccess && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+             hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        total += ms * 1e-3;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ok ? total / reps : -1.0;
 }
 
 }  // namespace mxs

@@ -355,6 +355,21 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
     }
 }
 
+// Value of the neighbouring lane across the whole wavefront: SHR gives lane
+// i the value of lane i - 1, SHL the value of lane i + 1 (DPP wave shifts;
+// the lane at the end of the wavefront receives 0).
+template <int CTRL> __device__ __forceinline__ double wave_shift(double v) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, 0xf, 0xf, false));
+    const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xf, 0xf, false));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+template <int CTRL> __device__ __forceinline__ float wave_shift(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveShr1 = 0x138;
+
 // Block form (windows of 3 or 5 rows): a workgroup requests all GIN input
 // rows of its chunk at once, GIN - NWY + 1 output rows, stages them in LDS
 // with their x halo (NWX > 1) and computes every output row of the chunk;
@@ -364,7 +379,13 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
 // second read is served by L2.  Rows and columns outside a non-periodic grid
 // are read from clamped addresses: they only meet outputs that are not
 // written (or padded taps of weight zero).
-template <typename T, int NWX, int NWY, int GIN, bool CLEAN>
+//
+// XS (x exchange by lanes, centred windows only: left = right = NWX / 2 <=
+// V): the x neighbours of a thread's V values come from the neighbouring
+// lanes by DPP wave shifts instead of an LDS row; the two lanes at the ends
+// of a wavefront load their outside neighbours themselves.  No LDS, no
+// barrier.
+template <typename T, int NWX, int NWY, int GIN, bool CLEAN, bool XS>
 __device__ __forceinline__ void block_body(const Stencil2DArgs &a, int strip, int chunk, unsigned char *smem) {
     using A = typename St<T>::acc;
     constexpr int V = St<T>::V;
@@ -408,10 +429,29 @@ __device__ __forceinline__ void block_body(const Stencil2DArgs &a, int strip, in
             }
         }
     }
+    constexpr int HX = NWX / 2;   // lane exchange: neighbours on each side
+    const int lane = t & 63;
+    // lane exchange: lane 0 loads the HX values left of its vector, lane 63
+    // the HX values right of it
+    A ev[GIN][HX > 0 ? HX : 1];
+    if constexpr (XS && HX > 0) {
+        if (lane == 0 || lane == 63) {
+#pragma unroll
+            for (int u = 0; u < GIN; ++u) {
+                const gptr<const T> rowp = in + in_row(u) * a.ld;
+#pragma unroll
+                for (int h = 0; h < HX; ++h) {
+                    long long c = lane == 0 ? ib - HX + h : ib + V + h;
+                    c = periodic ? wrap_fast(c, a.nx) : (c < 0 ? 0 : (c >= a.nx ? a.nx - 1 : c));
+                    ev[u][h] = to_acc<T>(gld<T>(rowp, c));
+                }
+            }
+        }
+    }
     A hv[HPT > 0 ? HPT : 1];
     const int hcount = GIN * 2 * PAD;
 #pragma unroll
-    for (int q = 0; q < HPT; ++q) {
+    for (int q = 0; q < (XS ? 0 : HPT); ++q) {
         const int h = min(t + q * nt, hcount - 1);
         const int u = h / (2 * PAD);
         const int hh = h - u * 2 * PAD;
@@ -428,8 +468,15 @@ __device__ __forceinline__ void block_body(const Stencil2DArgs &a, int strip, in
         for (int u = 0; u < GIN; ++u)
 #pragma unroll
             for (int v = 0; v < V; ++v) f[u][v] = top;
+        constexpr int HQ = XS ? 0 : HPT;
+        constexpr int EQ = XS ? HX : 0;
+        A ef[GIN][EQ > 0 ? EQ : 1];
 #pragma unroll
-        for (int q = 0; q < HPT; ++q) hf[q] = top;
+        for (int q = 0; q < HQ; ++q) hf[q] = top;
+#pragma unroll
+        for (int u = 0; u < GIN; ++u)
+#pragma unroll
+            for (int h = 0; h < EQ; ++h) ef[u][h] = top;
         for (int m = a.ncoe - 2; m >= 0; --m) {
             const A cm = coe[m];
 #pragma unroll
@@ -437,16 +484,41 @@ __device__ __forceinline__ void block_body(const Stencil2DArgs &a, int strip, in
 #pragma unroll
                 for (int v = 0; v < V; ++v) f[u][v] = f[u][v] * xin[u][v] + cm;
 #pragma unroll
-            for (int q = 0; q < HPT; ++q) hf[q] = hf[q] * hv[q] + cm;
+            for (int q = 0; q < HQ; ++q) hf[q] = hf[q] * hv[q] + cm;
+#pragma unroll
+            for (int u = 0; u < GIN; ++u)
+#pragma unroll
+                for (int h = 0; h < EQ; ++h) ef[u][h] = ef[u][h] * ev[u][h] + cm;
         }
 #pragma unroll
         for (int u = 0; u < GIN; ++u)
 #pragma unroll
             for (int v = 0; v < V; ++v) xin[u][v] = f[u][v];
 #pragma unroll
-        for (int q = 0; q < HPT; ++q) hv[q] = hf[q];
+        for (int q = 0; q < HQ; ++q) hv[q] = hf[q];
+#pragma unroll
+        for (int u = 0; u < GIN; ++u)
+#pragma unroll
+            for (int h = 0; h < EQ; ++h) ev[u][h] = ef[u][h];
     }
-    if constexpr (NWX > 1) {
+    // lane exchange: the window of every input row, columns ib - HX ..
+    // ib + V - 1 + HX
+    A xw[XS ? GIN : 1][XS ? V + 2 * HX : 1];
+    if constexpr (XS) {
+#pragma unroll
+        for (int u = 0; u < GIN; ++u) {
+#pragma unroll
+            for (int h = 0; h < HX; ++h) {
+                const A l = wave_shift<kDppWaveShr1>(xin[u][V - HX + h]);
+                const A r = wave_shift<kDppWaveShl1>(xin[u][h]);
+                xw[u][h] = lane == 0 ? ev[u][h] : l;
+                xw[u][HX + V + h] = lane == 63 ? ev[u][h] : r;
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) xw[u][HX + v] = xin[u][v];
+        }
+    }
+    if constexpr (NWX > 1 && !XS) {
 #pragma unroll
         for (int u = 0; u < GIN; ++u) {
             A *dst = lds + u * rowlen + PAD + t * V;
@@ -473,7 +545,14 @@ __device__ __forceinline__ void block_body(const Stencil2DArgs &a, int strip, in
         for (int v = 0; v < V; ++v) acc[v] = A(0);
 #pragma unroll
         for (int q = 0; q < NWY; ++q) {
-            if constexpr (NWX > 1) {
+            if constexpr (XS) {
+#pragma unroll
+                for (int p = 0; p < NWX; ++p) {
+                    const A wt = w[q * NWX + p];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) acc[v] = fma(wt, xw[k + q][v + p], acc[v]);
+                }
+            } else if constexpr (NWX > 1) {
                 A x[XW];
                 const A *lp = lds + (k + q) * rowlen + PAD + t * V - a.L;
 #pragma unroll
@@ -507,7 +586,7 @@ __device__ __forceinline__ void block_body(const Stencil2DArgs &a, int strip, in
     }
 }
 
-template <typename T, int NWX, int NWY, int GIN>
+template <typename T, int NWX, int NWY, int GIN, bool XS>
 __global__ void __launch_bounds__(256) stencil2d_block_kernel(const Stencil2DArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int strip, chunk;
@@ -522,18 +601,26 @@ __global__ void __launch_bounds__(256) stencil2d_block_kernel(const Stencil2DArg
     const long long W = static_cast<long long>(blockDim.x) * St<T>::V;
     // a strip whose vectors all lie inside the grid, aligned: vector loads only
     if (a.vec_ok && (strip + 1) * W <= a.nx)
-        block_body<T, NWX, NWY, GIN, true>(a, strip, chunk, smem_raw);
+        block_body<T, NWX, NWY, GIN, true, XS>(a, strip, chunk, smem_raw);
     else
-        block_body<T, NWX, NWY, GIN, false>(a, strip, chunk, smem_raw);
+        block_body<T, NWX, NWY, GIN, false, XS>(a, strip, chunk, smem_raw);
 }
 
 template <typename T, int NWX, int NWY, int GIN>
 hipError_t launch_block(const Stencil2DArgs &a, int threads, hipStream_t s) {
     using A = typename St<T>::acc;
     constexpr int V = St<T>::V;
-    const size_t lds = NWX > 1 ? static_cast<size_t>(GIN) * (2 * halo_pad<NWX, V>() + threads * V) * sizeof(A) : 0;
     const int grid = a.nstrips * a.nchunks;
-    hipLaunchKernelGGL((stencil2d_block_kernel<T, NWX, NWY, GIN>), dim3(grid), dim3(threads), lds, s, a);
+    if constexpr (NWX > 1 && NWX / 2 <= V) {
+        if (a.xshuffle) {
+            if (a.L != NWX / 2 || a.R != NWX / 2) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((stencil2d_block_kernel<T, NWX, NWY, GIN, true>), dim3(grid), dim3(threads), 0, s, a);
+            return hipGetLastError();
+        }
+    }
+    if (a.xshuffle) return hipErrorInvalidValue;
+    const size_t lds = NWX > 1 ? static_cast<size_t>(GIN) * (2 * halo_pad<NWX, V>() + threads * V) * sizeof(A) : 0;
+    hipLaunchKernelGGL((stencil2d_block_kernel<T, NWX, NWY, GIN, false>), dim3(grid), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
@@ -553,9 +640,12 @@ template <typename T>
 hipError_t dispatch_block(int nwx, int nwy, const Stencil2DArgs &a, int threads, hipStream_t s) {
 #define MXS_BCASE(X, Y, G) \
     if (nwx == X && nwy == Y && a.block_rows == G) return launch_block<T, X, Y, G>(a, threads, s);
-    MXS_BCASE(1, 3, 8) MXS_BCASE(1, 3, 16) MXS_BCASE(1, 5, 8) MXS_BCASE(1, 5, 16)
-    MXS_BCASE(3, 3, 8) MXS_BCASE(3, 3, 16) MXS_BCASE(3, 5, 8) MXS_BCASE(3, 5, 16)
-    MXS_BCASE(5, 3, 8) MXS_BCASE(5, 3, 16) MXS_BCASE(5, 5, 8) MXS_BCASE(5, 5, 16)
+    MXS_BCASE(1, 3, 8) MXS_BCASE(1, 3, 12) MXS_BCASE(1, 3, 16)
+    MXS_BCASE(1, 5, 8) MXS_BCASE(1, 5, 12) MXS_BCASE(1, 5, 16)
+    MXS_BCASE(3, 3, 8) MXS_BCASE(3, 3, 12) MXS_BCASE(3, 3, 16)
+    MXS_BCASE(3, 5, 8) MXS_BCASE(3, 5, 12) MXS_BCASE(3, 5, 16)
+    MXS_BCASE(5, 3, 8) MXS_BCASE(5, 3, 12) MXS_BCASE(5, 3, 16)
+    MXS_BCASE(5, 5, 8) MXS_BCASE(5, 5, 12) MXS_BCASE(5, 5, 16)
 #undef MXS_BCASE
     return hipErrorInvalidValue;
 }
@@ -574,7 +664,28 @@ hipError_t dispatch(int nwx, int nwy, const Stencil2DArgs &a, int threads, hipSt
     return hipErrorInvalidValue;
 }
 
+// Reads a buffer once (grid-stride, 16-byte loads) and writes nothing back
+// unless its words XOR to a fixed value (then one word of the same buffer,
+// which only serves this kernel): the loads replace the contents of the
+// memory-side cache with clean lines.
+typedef unsigned int v4u_t __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) cache_flush_kernel(void *buf, size_t n16) {
+    const gptr<const v4u_t> p = as_global(static_cast<const v4u_t *>(buf));
+    uint32_t x = 0;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n16;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const v4u_t v = p[i];
+        x ^= v.x ^ v.y ^ v.z ^ v.w;
+    }
+    if (x == 0x9e3779b9u) as_global(reinterpret_cast<uint32_t *>(buf))[0] = x;
+}
+
 }  // namespace
+
+hipError_t launch_cache_flush(void *buf, size_t bytes, hipStream_t s) {
+    hipLaunchKernelGGL(cache_flush_kernel, dim3(2048), dim3(256), 0, s, buf, bytes / 16);
+    return hipGetLastError();
+}
 
 int bucket_width(int taps) {
     if (taps <= 1) return 1;
@@ -586,11 +697,18 @@ int bucket_width(int taps) {
 }
 
 bool stencil2d_block_ok(int nwx, int nwy, int block_rows) {
-    return (nwx == 1 || nwx == 3 || nwx == 5) && (nwy == 3 || nwy == 5) && (block_rows == 8 || block_rows == 16);
+    return (nwx == 1 || nwx == 3 || nwx == 5) && (nwy == 3 || nwy == 5) &&
+           (block_rows == 8 || block_rows == 12 || block_rows == 16);
 }
 
-size_t stencil2d_lds_bytes(int dtype, int nwx, int nwy, int threads, int block_rows) {
-    if (nwx <= 1) return 0;
+bool stencil2d_xshuffle_ok(int dtype, int nwx, int nwy, int left, int right, int block_rows) {
+    const int V = dtype == F64 ? St<double>::V : dtype == F32 ? St<float>::V : St<bf16>::V;
+    return stencil2d_block_ok(nwx, nwy, block_rows) && nwx > 1 && nwx / 2 <= V && left == nwx / 2 &&
+           right == nwx / 2;
+}
+
+size_t stencil2d_lds_bytes(int dtype, int nwx, int nwy, int threads, int block_rows, int xshuffle) {
+    if (nwx <= 1 || xshuffle) return 0;
     const int V = dtype == F64 ? St<double>::V : dtype == F32 ? St<float>::V : St<bf16>::V;
     const int acc = dtype == F64 ? 8 : 4;
     const int pad = ((nwx - 1 + V - 1) / V) * V;

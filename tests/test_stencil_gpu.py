@@ -287,14 +287,17 @@ LAYOUTS = ["2,1,256,1", "4,0,256,0", "8,1,128,1", "16,0,128,0", "64,1,256,1", "1
            "3,1,64,0", "4,1,256,1", "16,1,256,1", "128,1,256,1", "8,0,256,1", "64,0,256,1",
            # block form (fifth field: input rows per workgroup; windows of 3 or 5
            # rows only, others keep their default layout)
-           "1,1,256,1,8", "1,0,128,0,8", "1,1,128,1,16", "1,0,256,0,16", "1,1,64,1,16"]
+           "1,1,256,1,8", "1,0,128,0,8", "1,1,128,1,16", "1,0,256,0,16", "1,1,64,1,16",
+           "1,1,256,1,12",
+           # block form, x neighbours by lane shifts (sixth field; centred windows)
+           "1,1,256,1,8,1", "1,0,128,0,12,1", "1,1,64,1,16,1"]
 LAYOUT_WINDOWS = [("X", (2, 2, 0, 0), None), ("Y", (0, 0, 2, 1), None), ("XY", (1, 2, 2, 1), None),
-                  ("XY", (1, 1, 1, 1), wl.CUBIC_MINUS_LINEAR)]
+                  ("XY", (1, 1, 1, 1), wl.CUBIC_MINUS_LINEAR), ("XY", (2, 2, 1, 1), None)]
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
-@pytest.mark.parametrize("direction,ext,coe", LAYOUT_WINDOWS, ids=["X", "Y", "XY", "XYfun"])
+@pytest.mark.parametrize("direction,ext,coe", LAYOUT_WINDOWS, ids=["X", "Y", "XY", "XYfun", "XY5x3"])
 def test_every_layout_keeps_parity(monkeypatch, layout, dt, direction, ext, coe):
     """Rows per workgroup, tile order, threads per workgroup and streaming
     stores change only the schedule: every layout matches the oracle in
@@ -313,13 +316,16 @@ BLOCK_WINDOWS = [("Y", (0, 0, 1, 1)), ("Y", (0, 0, 2, 2)), ("Y", (0, 0, 3, 0)), 
                  ("XY", (2, 1, 0, 2)), ("XY", (2, 2, 2, 2)), ("XY", (0, 1, 1, 0))]
 
 
-@pytest.mark.parametrize("layout", ["1,1,64,1,8", "1,0,128,0,16"])
+@pytest.mark.parametrize("layout", ["1,1,64,1,8", "1,0,128,0,16", "1,1,64,1,8,1", "1,0,256,0,12,1",
+                                    "1,1,128,1,16,1"])
 @pytest.mark.parametrize("shape", [(5, 9), (8, 70), (37, 45), (257, 129), (23, 1030)])
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
 def test_block_form_small_and_ragged_grids(monkeypatch, layout, shape, dt):
     """The block form on grids with fewer rows than one chunk, ragged last
     chunks and strips, unaligned pitches and padded windows, periodic and
-    not, with and without the point function."""
+    not, with and without the point function; with x neighbours from LDS
+    and, for the centred windows, from lane shifts (the other windows keep
+    their default layout)."""
     monkeypatch.setenv("MXS_STENCIL_TILE", layout)
     rng = np.random.default_rng(hash((shape, layout, dt)) % (1 << 32))
     u = rng.uniform(-1, 1, shape)
