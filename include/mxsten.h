@@ -139,6 +139,30 @@ mxs_status mxs_create_cyclic_solve(int bw, const double *coef, int geometry,
                                    const long long *offsets, int dtype,
                                    const void *rhs, void *x, mxs_plan *plan);
 
+/* ------------------------------------------------------------------------
+ * WENO advection: the periodic xy variant of Sec. 4.3, in which the weighted
+ * sum of the periodic XY stencil is replaced by a WENO evaluation of the
+ * advection term and the velocities are extra inputs:
+ *
+ *   out[j][i] = u[j][i] * phi_x + v[j][i] * phi_y
+ *
+ * phi_x is the fifth-order Hamilton-Jacobi WENO derivative (the level-set
+ * text the section cites) from the backward differences
+ * (phi[i+k] - phi[i+k-1]) / dx, k = -2..2, where u > 0, and from the forward
+ * differences (phi[i+k+1] - phi[i+k]) / dx, k = 2..-2, where u <= 0 (zero
+ * velocity contributes zero either way); phi_y likewise along j with v and
+ * dy.  Every index wraps (periodic grid).  Epsilon of the nonlinear weights:
+ * 1e-6 times the largest squared difference of the five, plus 1e-99.
+ * phi, u, v, out: device, ny rows of pitch ld, FP64 only (dtype MXS_F64,
+ * else MXS_ERR_UNSUPPORTED); out must not overlap phi, u or v
+ * (MXS_ERR_ALIAS).  Requires nx, ny >= 6.  mxs_compute evaluates,
+ * mxs_swap exchanges phi and out, mxs_set_io(plan, phi, out) rebinds them
+ * (u and v stay), mxs_autotune picks the tile layout.
+ * ---------------------------------------------------------------------- */
+mxs_status mxs_create_weno_adv(int nx, int ny, long long ld, double dx, double dy,
+                               int dtype, const void *phi, const void *u,
+                               const void *v, void *out, mxs_plan *plan);
+
 /* Run the plan on a stream: the stencil or the solve (cuStenCompute*). */
 mxs_status mxs_compute(mxs_plan plan, void *hip_stream);
 

@@ -83,6 +83,8 @@ _SIGS = {
     "mxs_ch_state": [_vp, _int, ctypes.POINTER(_vp), ctypes.POINTER(_vp)],
     "mxs_ch_steps_taken": [_vp, _llp],
     "mxs_ch_mass": [_vp, _dp, _vp],
+    "mxs_create_weno_adv": [_int, _int, _ll, ctypes.c_double, ctypes.c_double, _int, _vp, _vp, _vp, _vp,
+                            ctypes.POINTER(_vp)],
     "mxs_ch_coarsening": [_vp, _int, _dp, _dp, _vp],
     "mxs_ch_coarsening_noalloc": [_vp, _int, _dp, _dp, _vp],
     "mxs_destroy": [_vp],
@@ -166,6 +168,14 @@ def mxs_create_2d(nx, ny, ld, dir, bc, dtype, left, right, top, bottom, weights,
                            _as_dp(c), nc, _ptr(in_), _ptr(out))
     plan = _vp()
     _check(_lib.mxs_create_2d(ctypes.byref(d), ctypes.byref(plan)))
+    return plan.value
+
+
+def mxs_create_weno_adv(nx, ny, ld, dx, dy, dtype, phi, u, v, out):
+    """WENO advection plan (out = u phi_x + v phi_y, periodic)."""
+    plan = _vp()
+    _check(_lib.mxs_create_weno_adv(nx, ny, ld, dx, dy, dtype, _ptr(phi), _ptr(u), _ptr(v), _ptr(out),
+                                    ctypes.byref(plan)))
     return plan.value
 
 
