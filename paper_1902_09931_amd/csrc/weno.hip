@@ -27,27 +27,41 @@ constexpr int kWenoPad = 4;   // halo columns staged on each side (3 used), a wh
 
 // The WENO combination of five consecutive one-sided differences v1..v5,
 // ordered away from the upwind side (v3 the difference at the point): the
-// three third-order ENO candidates, their smoothness indicators, and the
-// nonlinear weights from the optimal ones 1/10, 6/10, 3/10, with epsilon
-// 1e-6 times the largest squared difference plus a floor of 1e-99.
+// three third-order ENO candidates, their smoothness indicators s_k, and the
+// nonlinear weights w_k = a_k / sum a, a_k = g_k / (s_k + eps)^2 with the
+// optimal weights g = 1/10, 6/10, 3/10 and eps = 1e-6 times the largest
+// squared difference plus 1e-99.
+//
+// Arithmetic: the candidates by multiplications with rounded constants
+// instead of divisions, and the weights with one division instead of four:
+// w_k = g_k prod_{m != k} d_m^2 / sum_l g_l prod_{m != l} d_m^2, d = s + eps,
+// the same ratio.  The d_m are first scaled by the same power of two
+// (exactly), so that the largest lies in [1/2, 1): since s_m <= 34 max v^2
+// and eps >= 1e-6 max v^2 (or all d_m = eps when every v is zero), every
+// scaled d_m is at least 1.4e-8 and no product underflows.
 __device__ __forceinline__ double weno5(double v1, double v2, double v3, double v4, double v5) {
-    const double p1 = v1 / 3.0 - 7.0 * v2 / 6.0 + 11.0 * v3 / 6.0;
-    const double p2 = -v2 / 6.0 + 5.0 * v3 / 6.0 + v4 / 3.0;
-    const double p3 = v3 / 3.0 + 5.0 * v4 / 6.0 - v5 / 6.0;
+    constexpr double third = 1.0 / 3.0, sixth = 1.0 / 6.0;
+    const double p1 = fma(v1, third, fma(v2, -7.0 * sixth, v3 * (11.0 * sixth)));
+    const double p2 = fma(v2, -sixth, fma(v3, 5.0 * sixth, v4 * third));
+    const double p3 = fma(v3, third, fma(v4, 5.0 * sixth, v5 * -sixth));
     double a = v1 - 2.0 * v2 + v3, b = v1 - 4.0 * v2 + 3.0 * v3;
-    const double s1 = 13.0 / 12.0 * (a * a) + 0.25 * (b * b);
+    const double s1 = fma(13.0 / 12.0, a * a, 0.25 * (b * b));
     a = v2 - 2.0 * v3 + v4;
     b = v2 - v4;
-    const double s2 = 13.0 / 12.0 * (a * a) + 0.25 * (b * b);
+    const double s2 = fma(13.0 / 12.0, a * a, 0.25 * (b * b));
     a = v3 - 2.0 * v4 + v5;
     b = 3.0 * v3 - 4.0 * v4 + v5;
-    const double s3 = 13.0 / 12.0 * (a * a) + 0.25 * (b * b);
+    const double s3 = fma(13.0 / 12.0, a * a, 0.25 * (b * b));
     const double m = fmax(fmax(fmax(v1 * v1, v2 * v2), fmax(v3 * v3, v4 * v4)), v5 * v5);
-    const double eps = 1e-6 * m + 1e-99;
-    const double d1 = s1 + eps, d2 = s2 + eps, d3 = s3 + eps;
-    const double a1 = 0.1 / (d1 * d1), a2 = 0.6 / (d2 * d2), a3 = 0.3 / (d3 * d3);
-    const double sum = a1 + a2 + a3;
-    return (a1 / sum) * p1 + (a2 / sum) * p2 + (a3 / sum) * p3;
+    const double eps = fma(1e-6, m, 1e-99);
+    double d1 = s1 + eps, d2 = s2 + eps, d3 = s3 + eps;
+    const int ex = __builtin_amdgcn_frexp_exp(fmax(fmax(d1, d2), d3));
+    d1 = __builtin_amdgcn_ldexp(d1, -ex);
+    d2 = __builtin_amdgcn_ldexp(d2, -ex);
+    d3 = __builtin_amdgcn_ldexp(d3, -ex);
+    const double q1 = d1 * d1, q2 = d2 * d2, q3 = d3 * d3;
+    const double n1 = 0.1 * (q2 * q3), n2 = 0.6 * (q1 * q3), n3 = 0.3 * (q1 * q2);
+    return fma(n1, p1, fma(n2, p2, n3 * p3)) / (n1 + n2 + n3);
 }
 
 // The upwind WENO derivative from seven consecutive values f[0..6] centred on
