@@ -218,6 +218,19 @@ mxs_status mxs_ch_ensemble_create(int count, const int *nx, const int *ny,
  * a captured HIP graph (one per rotation of the three buffers). */
 mxs_status mxs_ch_step(mxs_plan plan, int nsteps, int use_graph, void *hip_stream);
 
+/* How a step is launched.  MXS_CH_SEPARATE: one launch per kernel of the
+ * step (right-hand side, row solves per register class, three column
+ * phases), each covering every instance.  MXS_CH_PERSISTENT: the whole step
+ * of every instance in one cooperative launch whose workgroups stay resident
+ * and meet at a grid barrier between the phases (rows of at most 1024
+ * elements; else MXS_ERR_UNSUPPORTED, as when the device cannot hold the
+ * grid).  The barrier's wait is bounded: a barrier that times out makes the
+ * launch end early, and the next mxs_ch_mass returns MXS_ERR_HIP.  Plans
+ * start in MXS_CH_SEPARATE; mxs_autotune times both and keeps the faster.
+ * With use_graph the persistent launch is captured in the step's graph. */
+enum { MXS_CH_SEPARATE = 0, MXS_CH_PERSISTENT = 1 };
+mxs_status mxs_ch_set_step_mode(mxs_plan plan, int mode);
+
 /* Device pointers of C^{n-1} and C^n of instance k (k = 0 for one grid). */
 mxs_status mxs_ch_state(mxs_plan plan, int k, void **c_prev, void **c_cur);
 

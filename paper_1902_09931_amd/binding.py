@@ -40,6 +40,7 @@ MXS_X, MXS_Y, MXS_XY = 0, 1, 2
 MXS_NP, MXS_P = 0, 1
 MXS_F64, MXS_F32, MXS_BF16 = 0, 1, 2
 MXS_LINES_RAGGED, MXS_LINES_ROWS, MXS_LINES_COLS = 0, 1, 2
+MXS_CH_SEPARATE, MXS_CH_PERSISTENT = 0, 1
 
 
 class MxsError(RuntimeError):
@@ -86,6 +87,7 @@ _SIGS = {
     "mxs_create_weno_adv": [_int, _int, _ll, ctypes.c_double, ctypes.c_double, _int, _vp, _vp, _vp, _vp,
                             ctypes.POINTER(_vp)],
     "mxs_ch_coarsening": [_vp, _int, _dp, _dp, _vp],
+    "mxs_ch_set_step_mode": [_vp, _int],
     "mxs_ch_coarsening_noalloc": [_vp, _int, _dp, _dp, _vp],
     "mxs_destroy": [_vp],
     "mxs_autotune": [_vp, _vp],
@@ -277,6 +279,11 @@ def mxs_ch_coarsening(plan, k=0, stream=None):
     sv, kv = ctypes.c_double(), ctypes.c_double()
     _check(_lib.mxs_ch_coarsening(plan, k, ctypes.byref(sv), ctypes.byref(kv), _stream(stream)))
     return sv.value, kv.value
+
+
+def mxs_ch_set_step_mode(plan, mode):
+    """MXS_CH_SEPARATE or MXS_CH_PERSISTENT (one launch per step)."""
+    _check(_lib.mxs_ch_set_step_mode(plan, mode))
 
 
 def mxs_ch_coarsening_noalloc(plan, k=0, stream=None):

@@ -11,12 +11,14 @@
 // HIP graph) per rotation.
 #include "ch.h"
 #include "diag.h"
+#include "persist.h"
 #include "plans.h"
 #include "solve.h"
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <numeric>
 #include <vector>
 
@@ -91,11 +93,31 @@ struct CHPlan final : mxs_plan_s {
     hipStream_t cap = nullptr;
     hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
 
+    // persistent step (one cooperative launch per step): eligible when every
+    // row fits register class kPersistNBMax; bar holds the grid barrier's
+    // words (arrivals, generation, exits, error)
+    bool persistent = false, persist_ok = false;
+    int persist_grid = 0, persist_nbmax = 1, spin_limit = 1 << 22;
+    DevBuf bar;
+
     CHPlan() : mxs_plan_s(KIND_CH) {}
     ~CHPlan() override {
         drop_graphs();
         if (cap) (void)hipStreamDestroy(cap);
         if (mass_host) (void)hipHostFree(mass_host);
+        if (flag_host) (void)hipHostFree(flag_host);
+    }
+    unsigned *flag_host = nullptr;
+
+    // Run steps as one persistent launch (on) or as the separate launches
+    // (off); the right-hand side tables follow the workgroup size of the mode.
+    mxs_status set_persistent(bool on, int rows) {
+        if (on && !persist_ok) return fail(MXS_ERR_UNSUPPORTED, "this plan cannot run the persistent step");
+        drop_graphs();
+        persist_nograph = false;
+        persistent = on;
+        if (on) rhs_threads = kPersistThreads;
+        return build_rhs(rows);
     }
 
     int ninst() const { return static_cast<int>(inst.size()); }
@@ -113,6 +135,24 @@ struct CHPlan final : mxs_plan_s {
     }
 
     hipError_t enqueue(int r, hipStream_t s) {
+        if (persistent) {
+            PersistArgs pa{};
+            pa.rhs = static_cast<const RhsInst *>(rhs_d[r].ptr);
+            pa.rhs_map = map_of(rhs_map);
+            pa.rhs_blocks = rhs_blocks;
+            pa.rows = static_cast<const RowsInst *>(rows_d.ptr);
+            pa.rows_map = map_of(rows_map);
+            pa.row_lines = row_lines;
+            pa.cols = static_cast<const ColsInst *>(cols_d[r].ptr);
+            pa.colsAC_map = map_of(colsAC_map);
+            pa.colsB_map = map_of(colsB_map);
+            pa.colsAC = colsAC;
+            pa.colsB = colsB;
+            pa.bar = static_cast<unsigned *>(bar.ptr);
+            pa.spin_limit = spin_limit;
+            pa.stage_bytes = static_cast<int>(persist_stage_bytes(dtype, persist_nbmax));
+            return launch_ch_persistent(dtype, persist_nbmax, pa, persist_grid, s);
+        }
         hipError_t e = launch_ch_rhs(dtype, static_cast<const RhsInst *>(rhs_d[r].ptr),
                                      map_of(rhs_map), rhs_blocks, rhs_threads, s);
         if (e != hipSuccess) return e;
@@ -143,13 +183,24 @@ struct CHPlan final : mxs_plan_s {
         return e;
     }
 
+    // set when the runtime cannot capture the cooperative launch of the
+    // persistent step: its steps are then launched directly
+    bool persist_nograph = false;
+
     mxs_status step(int nsteps, bool use_graph, hipStream_t s) {
         for (int k = 0; k < nsteps; ++k) {
             const int r = static_cast<int>(steps % 3);
             hipError_t e;
-            if (use_graph) {
+            if (use_graph && !(persistent && persist_nograph)) {
                 if (!exec[r]) {
                     e = capture(r);
+                    if (e != hipSuccess && persistent) {
+                        (void)hipGetLastError();
+                        persist_nograph = true;
+                        drop_graphs();
+                        --k;
+                        continue;
+                    }
                     if (e != hipSuccess) return hip_fail(e, "graph capture of the step");
                 }
                 e = hipGraphLaunch(exec[r], s);
@@ -170,8 +221,17 @@ struct CHPlan final : mxs_plan_s {
         if (e == hipSuccess)
             e = hipMemcpyAsync(mass_host, mass_out.ptr, sizeof(double) * ninst(),
                                hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess && bar.ptr)
+            e = hipMemcpyAsync(flag_host, static_cast<unsigned *>(bar.ptr) + 3, sizeof(unsigned),
+                               hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "mass reduction");
+        if (bar.ptr && *flag_host) {
+            *flag_host = 0;
+            e = hipMemcpy(static_cast<unsigned *>(bar.ptr) + 3, flag_host, sizeof(unsigned), hipMemcpyHostToDevice);
+            return fail(MXS_ERR_HIP, "a grid barrier of the persistent step timed out (workgroups not co-resident)%s",
+                        e == hipSuccess ? "" : "; clearing the error word failed");
+        }
         bool finite = true;
         for (int g = 0; g < ninst(); ++g) {
             out[g] = mass_host[g];
@@ -319,6 +379,7 @@ struct CHPlan final : mxs_plan_s {
         const int r = static_cast<int>(steps % 3);
         struct Cand {
             int threads, rows, w;
+            bool pers;
             double t;
         };
         std::vector<Cand> cands;
@@ -327,30 +388,58 @@ struct CHPlan final : mxs_plan_s {
                 for (int w : {1, 2, 4}) {
                     if (line_lds_bytes(max_nx, w) > static_cast<size_t>(device_lds_limit())) continue;
                     if (!row_ranges.empty() && w != row_nw) continue;   // no LDS kernel to shape
-                    cands.push_back({threads, rows, w, 1e30});
+                    cands.push_back({threads, rows, w, false, 1e30});
                 }
+        // the persistent step (one launch), right-hand side chunks of each height
+        if (persist_ok)
+            for (int rows : {4, 8, 16, 32}) cands.push_back({kPersistThreads, rows, row_nw, true, 1e30});
         if (cands.empty()) return MXS_OK;
         for (int pass = 0; pass < 2; ++pass)
             for (Cand &c : cands) {
+                persistent = c.pers;
                 rhs_threads = c.threads;
                 mxs_status st = build_rhs(c.rows);
                 if (st) return st;
                 set_row_waves(c.w);
                 const double t = time_launches([&] { return enqueue(r, s); }, s, 2, 10);
-                if (t < 0) return hip_fail(hipGetLastError(), "autotune launch");
+                if (t < 0) {
+                    persistent = false;
+                    return hip_fail(hipGetLastError(), "autotune launch");
+                }
                 c.t = std::min(c.t, t);
             }
         const Cand *best = &cands.front();
         for (const Cand &c : cands)
             if (c.t < best->t) best = &c;
+        for (const Cand &c : cands)
+            if (c.pers && (!best_persist || c.t < best_persist_t)) {
+                best_persist = true;
+                best_persist_t = c.t;
+            }
+        for (const Cand &c : cands)
+            if (!c.pers && c.t < best_graph_t) best_graph_t = c.t;
         set_row_waves(best->w);
+        persistent = best->pers;
+        persist_nograph = false;
         rhs_threads = best->threads;
         return build_rhs(best->rows);
     }
 
+    // step times of the best candidate of each mode at the last autotune
+    bool best_persist = false;
+    double best_persist_t = 0, best_graph_t = 1e30;
+
     void info(char *buf, int len) const override {
-        int n = snprintf(buf, len, "ch instances=%d dtype=%d rhs_rows=%d rhs_threads=%d rhs_blocks=%d cols_blocks=%d",
-                         ninst(), dtype, rhs_rows, rhs_threads, rhs_blocks, colsAC);
+        const int launches = persistent ? 1 : 1 + (row_ranges.empty() ? 1 : static_cast<int>(row_ranges.size())) + 3;
+        int n = snprintf(buf, len, "ch instances=%d dtype=%d step=%s launches_per_step=%d rhs_rows=%d rhs_threads=%d "
+                         "rhs_blocks=%d cols_blocks=%d",
+                         ninst(), dtype, persistent ? "persistent" : "separate", launches, rhs_rows, rhs_threads,
+                         rhs_blocks, colsAC);
+        if (persistent && n < len)
+            n += snprintf(buf + n, len - n, " persist_grid=%d persist_graph=%d", persist_grid, persist_nograph ? 0 : 1);
+        if (best_persist && n < len)
+            n += snprintf(buf + n, len - n, " tuned_us_separate=%.1f tuned_us_persistent=%.1f", best_graph_t * 1e6,
+                          best_persist_t * 1e6);
         if (row_ranges.empty() && n < len)
             n += snprintf(buf + n, len - n, " row_kernel=lds row_waves=%d row_grid=%d", row_nw, row_grid);
         for (size_t q = 0; q < row_ranges.size() && n < len; ++q)
@@ -487,7 +576,33 @@ struct CHPlan final : mxs_plan_s {
         if (e == hipSuccess) e = partial.alloc(sizeof(double) * mass_blocks);
         if (e == hipSuccess) e = mass_out.alloc(sizeof(double) * n);
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&mass_host), sizeof(double) * n, 0);
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&flag_host), sizeof(unsigned), 0);
         if (e != hipSuccess) return hip_fail(e, "plan tables upload");
+        *flag_host = 0;
+
+        // the persistent step: every row in a register class up to
+        // kPersistNBMax, and a grid of as many workgroups as the CUs hold
+        persist_ok = false;
+        if (reg_rows && maxnx <= kPersistNBMax * kWaveBlock) {
+            persist_nbmax = 1;
+            for (const Inst &I : inst) persist_nbmax = std::max(persist_nbmax, wave_nb(I.nx));
+            int per_cu = 0;
+            if (persist_occupancy(dtype, persist_nbmax, &per_cu) == hipSuccess && per_cu > 0) {
+                persist_grid = per_cu * device_cu_count();
+                e = bar.alloc(4 * sizeof(unsigned));
+                if (e == hipSuccess) e = hipMemset(bar.ptr, 0, 4 * sizeof(unsigned));
+                if (e != hipSuccess) return hip_fail(e, "grid barrier allocation");
+                persist_ok = true;
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+        if (const char *env = getenv("MXS_PERSIST_SPIN")) spin_limit = std::max(0, atoi(env));
+        if (const char *env = getenv("MXS_CH_STEP"))
+            if (env[0] == 'p' && persist_ok) {
+                mxs_status st = set_persistent(true, 0);
+                if (st) return st;
+            }
         return MXS_OK;
     }
 };
@@ -584,6 +699,15 @@ mxs_status mxs_ch_step(mxs_plan plan, int nsteps, int use_graph, void *hip_strea
     if (!p) return fail(MXS_ERR_BAD_HANDLE, "not a Cahn-Hilliard plan");
     if (nsteps < 0) return fail(MXS_ERR_INVALID_ARG, "nsteps < 0");
     return p->step(nsteps, use_graph != 0, static_cast<hipStream_t>(hip_stream));
+}
+
+mxs_status mxs_ch_set_step_mode(mxs_plan plan, int mode) {
+    CHPlan *p = as_ch(plan);
+    if (!p) return fail(MXS_ERR_BAD_HANDLE, "not a Cahn-Hilliard plan");
+    if (mode != MXS_CH_SEPARATE && mode != MXS_CH_PERSISTENT)
+        return fail(MXS_ERR_INVALID_ARG, "mode must be MXS_CH_SEPARATE or MXS_CH_PERSISTENT");
+    if (mode == MXS_CH_SEPARATE && p->persistent) p->rhs_threads = kRhsThreads;
+    return p->set_persistent(mode == MXS_CH_PERSISTENT, p->rhs_rows);
 }
 
 mxs_status mxs_ch_state(mxs_plan plan, int k, void **c_prev, void **c_cur) {

@@ -458,3 +458,139 @@ def test_ch_ensemble_64_reduced_precision_against_oracle(dt_name, bound20, bound
           f"{max(serr20.values()):.3e} (20 steps), {max(serr500.values()):.3e} (500 steps)")
     assert max(err20.values()) <= bound20
     assert max(err500.values()) <= bound500
+
+
+# --- the persistent step (one launch per step) -------------------------------------
+
+def ensemble(sizes, dt_name, seed0=30):
+    c0s = [round_to(wl.ch_initial(ny, nx, seed=seed0 + k), dt_name) for k, (ny, nx) in enumerate(sizes)]
+    tdt = TORCH[dt_name]
+    bufs = [[torch.from_numpy(np.ascontiguousarray(c)).to(tdt).cuda() for _ in range(2)] +
+            [torch.zeros(c.shape, dtype=tdt, device="cuda")] for c in c0s]
+    nx = [s[1] for s in sizes]
+    ny = [s[0] for s in sizes]
+    dxs = [2 * math.pi / v for v in nx]
+    dys = [2 * math.pi / v for v in ny]
+    dts = [0.1 * d * d for d in dxs]
+    plan = b.mxs_ch_ensemble_create(nx, ny, dxs, dys, dts, D, GAMMA, code(dt_name),
+                                    [q[0] for q in bufs], [q[1] for q in bufs], [q[2] for q in bufs])
+    return plan, bufs, c0s, dxs, dys, dts
+
+
+def currents(plan, bufs):
+    out = []
+    for k, q in enumerate(bufs):
+        _, cur = b.mxs_ch_state(plan, k)
+        out.append(ptr_tensor(cur, q).double().cpu().numpy())
+    return out
+
+
+PERSIST_SIZES = [(64, 64), (96, 96), (40, 600), (128, 128), (24, 1000), (40, 72), (256, 256), (33, 1024)]
+
+
+@pytest.mark.parametrize("dt_name", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_persistent_step_matches_separate_launches(dt_name, use_graph):
+    """The whole ensemble step in one persistent launch gives bit-for-bit the
+    states of the separate launches (the same work items with the same
+    arithmetic), in every storage dtype, eager and graph-replayed; FP64 also
+    matches the oracle.  The plan reports one launch per step."""
+    nsteps = 12
+    runs = []
+    for mode in (b.MXS_CH_SEPARATE, b.MXS_CH_PERSISTENT):
+        plan, bufs, c0s, dxs, dys, dts = ensemble(PERSIST_SIZES, dt_name)
+        try:
+            b.mxs_ch_set_step_mode(plan, mode)
+            info = b.mxs_plan_info(plan)
+            b.mxs_ch_step(plan, nsteps, use_graph)
+            torch.cuda.synchronize()
+            b.mxs_ch_mass(plan, len(PERSIST_SIZES))     # raises if a grid barrier failed
+            runs.append((info, currents(plan, bufs)))
+        finally:
+            b.mxs_destroy(plan)
+    assert "step=separate" in runs[0][0] and "launches_per_step=1 " not in runs[0][0]
+    assert "step=persistent launches_per_step=1 " in runs[1][0]
+    for a, p in zip(runs[0][1], runs[1][1]):
+        assert np.array_equal(a, p)
+    if dt_name == "f64":
+        for k, c0 in enumerate(c0s):
+            _, oc = oracle.ch_run(c0, c0, nsteps, dxs[k], dys[k], dts[k], D, GAMMA)
+            assert rel_err(runs[1][1][k], oc) <= 1e-12
+
+
+def test_persistent_step_single_grid_and_graph_replays():
+    """One 1024^2 FP64 grid: persistent graph replays over 30 steps equal the
+    persistent eager launches, then the separate launches, bit for bit."""
+    c0 = wl.ch_initial(1024, 1024, seed=2)
+    res = []
+    for mode, graph in ((b.MXS_CH_PERSISTENT, True), (b.MXS_CH_PERSISTENT, False), (b.MXS_CH_SEPARATE, True)):
+        g = Grid(c0)
+        try:
+            b.mxs_ch_set_step_mode(g.plan, mode)
+            for _ in range(3):
+                b.mxs_ch_step(g.plan, 10, graph)
+                torch.cuda.synchronize()
+            b.mxs_ch_mass(g.plan)
+            res.append(g.state())
+        finally:
+            g.close()
+    for r in res[1:]:
+        assert np.array_equal(r[0], res[0][0]) and np.array_equal(r[1], res[0][1])
+
+
+def test_persistent_step_rejects_wide_rows():
+    g = Grid(wl.ch_initial(16, 2048, seed=3))
+    try:
+        with pytest.raises(b.MxsError) as e:
+            b.mxs_ch_set_step_mode(g.plan, b.MXS_CH_PERSISTENT)
+        assert e.value.status == b.MXS_ERR_UNSUPPORTED
+        with pytest.raises(b.MxsError) as e:
+            b.mxs_ch_set_step_mode(g.plan, 7)
+        assert e.value.status == b.MXS_ERR_INVALID_ARG
+        b.mxs_ch_step(g.plan, 2, True)      # the separate launches still serve it
+        b.mxs_ch_mass(g.plan)
+    finally:
+        g.close()
+
+
+def test_persistent_barrier_timeout_is_reported(monkeypatch):
+    """With the barrier's spin limit forced to zero from the host, every
+    waiting workgroup gives up at once: the launch ends early, the next
+    mxs_ch_mass reports MXS_ERR_HIP, and the plan works again after a
+    normal plan has run (the counters are reset by the last workgroup)."""
+    monkeypatch.setenv("MXS_PERSIST_SPIN", "0")
+    g = Grid(wl.ch_initial(128, 128, seed=4))
+    try:
+        b.mxs_ch_set_step_mode(g.plan, b.MXS_CH_PERSISTENT)
+        b.mxs_ch_step(g.plan, 2, False)
+        torch.cuda.synchronize()
+        with pytest.raises(b.MxsError) as e:
+            b.mxs_ch_mass(g.plan)
+        assert e.value.status == b.MXS_ERR_HIP and "grid barrier" in str(e.value)
+    finally:
+        g.close()
+    monkeypatch.delenv("MXS_PERSIST_SPIN")
+    c0 = wl.ch_initial(128, 128, seed=4)
+    g = Grid(c0)
+    try:
+        b.mxs_ch_set_step_mode(g.plan, b.MXS_CH_PERSISTENT)
+        b.mxs_ch_step(g.plan, 3, True)
+        torch.cuda.synchronize()
+        b.mxs_ch_mass(g.plan)
+        _, oc = oracle.ch_run(c0, c0, 3, g.dx, g.dy, g.dt, D, GAMMA)
+        assert rel_err(g.state()[1], oc) <= 1e-12
+    finally:
+        g.close()
+
+
+def test_autotune_times_both_step_forms():
+    plan, bufs, c0s, dxs, dys, dts = ensemble(PERSIST_SIZES[:5], "f32")
+    try:
+        b.mxs_autotune(plan)
+        info = b.mxs_plan_info(plan)
+        assert "tuned_us_separate=" in info and "tuned_us_persistent=" in info
+        b.mxs_ch_step(plan, 4, True)
+        torch.cuda.synchronize()
+        b.mxs_ch_mass(plan, 5)
+    finally:
+        b.mxs_destroy(plan)
