@@ -102,6 +102,51 @@ typedef struct {
 mxs_status mxs_create_2d(const mxs_stencil2d_desc *desc, mxs_plan *plan);
 
 /* ------------------------------------------------------------------------
+ * 2D stencils with a user function (the function-pointer variants of
+ * Sec. 4.2, one data set per input as in their multi-input forms).  The
+ * function is given as HIP source and compiled for the device when the plan
+ * is created (hipRTC); it must define
+ *
+ *   __device__ mxs_real NAME(const mxs_real *const *w, const mxs_real *coe,
+ *                            int loc);
+ *
+ * where mxs_real is double for MXS_F64 and float for MXS_F32 / MXS_BF16
+ * (the library defines it before the source), w[k] is the window of input k
+ * in window order ((top+bottom+1)*(left+right+1) values, row by row from the
+ * top left, left to right: element (b+top)*(left+right+1) + (a+left) is the
+ * input at offset (a, b)), coe the coefficients and loc = top*(left+right+1)
+ * + left the position of the point itself, so that the function can index
+ * relative to loc as the paper's does.  The return value is stored, rounded
+ * to the storage dtype, at the point.  Periodic: every index wraps.
+ * Non-periodic: only points whose window lies inside the grid are written;
+ * the others are left untouched.  Every input and the output share nx, ny,
+ * ld and dtype; out must not overlap an input.  A source that does not
+ * compile returns MXS_ERR_INVALID_ARG with the compiler's log in
+ * mxs_last_error().  mxs_compute runs it; mxs_swap exchanges input 0 and
+ * out; mxs_set_io rebinds input 0 and out.
+ * ---------------------------------------------------------------------- */
+#define MXS_MAX_FN_INPUTS 4
+#define MXS_MAX_FN_COE 64
+typedef struct {
+    int nx, ny;                  /* grid extents (x contiguous) */
+    long long ld;                /* row pitch in elements, >= nx */
+    int dir;                     /* MXS_X, MXS_Y or MXS_XY */
+    int bc;                      /* MXS_NP or MXS_P */
+    int dtype;                   /* storage dtype of every input and out */
+    int left, right;             /* x extents of the window */
+    int top, bottom;             /* y extents of the window */
+    int ninputs;                 /* 1 .. MXS_MAX_FN_INPUTS */
+    const void *const *inputs;   /* host array of ninputs device pointers */
+    void *out;                   /* device */
+    const double *coe;           /* host, ncoe coefficients (copied), or NULL */
+    int ncoe;                    /* 0 .. MXS_MAX_FN_COE */
+    const char *source;          /* HIP source defining the function */
+    const char *name;            /* the function's name (an identifier) */
+} mxs_stencil2d_fn_desc;
+
+mxs_status mxs_create_2d_fn(const mxs_stencil2d_fn_desc *desc, mxs_plan *plan);
+
+/* ------------------------------------------------------------------------
  * Batched 1D stencils over nbatch uneven signals stored back to back:
  * signal b is in[offsets[b] .. offsets[b+1]-1] (the batched 1D form of the
  * abstract).  Each signal is the MXS_X stencil of a one-row grid of length

@@ -66,8 +66,20 @@ _dp = ctypes.POINTER(ctypes.c_double)
 _llp = ctypes.POINTER(ctypes.c_longlong)
 _ip = ctypes.POINTER(ctypes.c_int)
 
+class mxs_stencil2d_fn_desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("ld", ctypes.c_longlong),
+                ("dir", ctypes.c_int), ("bc", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("left", ctypes.c_int), ("right", ctypes.c_int),
+                ("top", ctypes.c_int), ("bottom", ctypes.c_int),
+                ("ninputs", ctypes.c_int), ("inputs", ctypes.POINTER(ctypes.c_void_p)),
+                ("out", ctypes.c_void_p),
+                ("coe", ctypes.POINTER(ctypes.c_double)), ("ncoe", ctypes.c_int),
+                ("source", ctypes.c_char_p), ("name", ctypes.c_char_p)]
+
+
 _SIGS = {
     "mxs_create_2d": [ctypes.POINTER(mxs_stencil2d_desc), ctypes.POINTER(_vp)],
+    "mxs_create_2d_fn": [ctypes.POINTER(mxs_stencil2d_fn_desc), ctypes.POINTER(_vp)],
     "mxs_create_1d_batch": [_int, _llp, _int, _int, _int, _int, _dp, _dp, _int, _vp, _vp,
                             ctypes.POINTER(_vp)],
     "mxs_create_cyclic_solve": [_int, _dp, _int, _int, _int, _ll, _int, _llp, _int, _vp, _vp,
@@ -170,6 +182,21 @@ def mxs_create_2d(nx, ny, ld, dir, bc, dtype, left, right, top, bottom, weights,
                            _as_dp(c), nc, _ptr(in_), _ptr(out))
     plan = _vp()
     _check(_lib.mxs_create_2d(ctypes.byref(d), ctypes.byref(plan)))
+    return plan.value
+
+
+def mxs_create_2d_fn(nx, ny, ld, dir, bc, dtype, left, right, top, bottom, inputs, out, coe, source,
+                     name):
+    """Stencil with a user function compiled at plan creation (HIP source
+    defining `__device__ mxs_real name(const mxs_real *const *w, const
+    mxs_real *coe, int loc)`), over one or more inputs."""
+    ins = (ctypes.c_void_p * len(inputs))(*[_ptr(t) for t in inputs])
+    c, nc = _dbl_array(coe)
+    d = mxs_stencil2d_fn_desc(nx, ny, ld, dir, bc, dtype, left, right, top, bottom, len(inputs),
+                              ctypes.cast(ins, ctypes.POINTER(ctypes.c_void_p)), _ptr(out), _as_dp(c), nc,
+                              source.encode(), name.encode())
+    plan = _vp()
+    _check(_lib.mxs_create_2d_fn(ctypes.byref(d), ctypes.byref(plan)))
     return plan.value
 
 

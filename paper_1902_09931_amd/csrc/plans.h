@@ -6,7 +6,7 @@
 
 #include <stddef.h>
 
-enum PlanKind { KIND_STENCIL2D = 1, KIND_STENCIL1D = 2, KIND_SOLVE = 3, KIND_CH = 4, KIND_WENO = 5 };
+enum PlanKind { KIND_STENCIL2D = 1, KIND_STENCIL1D = 2, KIND_SOLVE = 3, KIND_CH = 4, KIND_WENO = 5, KIND_FN = 6 };
 
 struct mxs_plan_s {
     int kind;
