@@ -16,7 +16,8 @@ algorithmic 16 bytes per point), the oracle timed on the host cores on a
 bounded sample, and further sections under "extra": the FP32 stencil set,
 batched ragged 1D stencils and cyclic tridiagonal solves (65536 lines), the
 ADI Cahn-Hilliard step on 1024^2 and 4096^2 FP64 grids (steps/s), the
-64-grid FP32/BF16 ensemble against the FP64 path, and a device copy ceiling.
+64-grid FP32/BF16 ensemble against the FP64 path, the WENO advection
+variant, and a copy ceiling (the library's identity stencil).
 Only the cpu_baseline leg uses the oracle.
 """
 import argparse
@@ -313,10 +314,17 @@ def bench_ch(torch, b, wl, n, steps, warmup):
     layout = b.mxs_plan_info(p)
     sec, _ = time_loop(torch, lambda: b.mxs_ch_step(p, 1, True), steps, warmup)
     m = b.mxs_ch_mass(p)[0]
+    forms = {}
+    if n <= 1024:      # rows of at most 1024 elements: both step forms
+        for mode, key in ((b.MXS_CH_PERSISTENT, "persistent"), (b.MXS_CH_SEPARATE, "separate")):
+            b.mxs_ch_set_step_mode(p, mode)
+            fs, _ = time_loop(torch, lambda: b.mxs_ch_step(p, 1, True), steps, warmup)
+            forms[f"{key}_steps_per_s"] = steps / fs
+        b.mxs_ch_mass(p)
     b.mxs_destroy(p)
     per = sec / steps
     floor = 56 * n * n
-    return {"steps_timed": steps, "s_per_step": per, "steps_per_s": 1.0 / per, "layout": layout,
+    return {"steps_timed": steps, "s_per_step": per, "steps_per_s": 1.0 / per, "layout": layout, **forms,
             "floor_bytes_per_step": floor, "gb_per_s_at_floor": floor / per / 1e9,
             "frac_hbm_peak_at_floor": floor / per / 1e9 / HBM_PEAK_GBS,
             "mass_drift": abs(m - float(c0.sum())) / float(abs(c0).sum())}
@@ -341,8 +349,15 @@ def bench_ensemble(torch, b, wl, steps, warmup):
         b.mxs_autotune(p)
         out[f"ensemble_{name}_layout"] = b.mxs_plan_info(p)
         sec, _ = time_loop(torch, lambda: b.mxs_ch_step(p, 1, True), steps, warmup)
-        b.mxs_destroy(p)
         out[f"ensemble_{name}_steps_per_s"] = steps / sec
+        # both step forms, each graph-replayed: one persistent launch per
+        # step, and the separate launches
+        for mode, key in ((b.MXS_CH_PERSISTENT, "persistent"), (b.MXS_CH_SEPARATE, "separate")):
+            b.mxs_ch_set_step_mode(p, mode)
+            sec, _ = time_loop(torch, lambda: b.mxs_ch_step(p, 1, True), steps, warmup)
+            out[f"ensemble_{name}_{key}_steps_per_s"] = steps / sec
+        b.mxs_ch_mass(p, len(sizes))       # raises if a grid barrier failed
+        b.mxs_destroy(p)
         del bufs
     bufs = [ch_buffers(torch, c0, torch.float64) for c0 in c0s]
     plans = [b.mxs_ch_create(n, n, d, d, t, 1.0, 0.01, b.MXS_F64, *q)
@@ -366,15 +381,40 @@ def bench_ensemble(torch, b, wl, steps, warmup):
     return out
 
 
-def copy_ceiling(torch):
-    """Device-to-device copy of 1 GiB (torch's copy kernel): read + write bytes / time."""
+def copy_ceiling(torch, b, wl, n=8192):
+    """Copy ceilings, read + write bytes / time: the library's identity
+    stencil (a one-tap X window of weight 1, i.e. the stencil kernel as a
+    plain streaming copy, autotuned, over the same rotation of 2 GiB of
+    buffers as the stencil set) and, for context, torch's copy kernel on
+    1 GiB."""
+    u0 = torch.from_numpy(wl.uniform_grid(n, n, seed=1)).cuda()
+    npairs = max(2, (2 << 30) // (2 * 8 * n * n))
+    ins = [u0] + [u0.clone() for _ in range(npairs - 1)]
+    outs = [torch.empty_like(u0) for _ in range(npairs)]
+    ps = [b.mxs_create_2d(n, n, n, b.MXS_X, b.MXS_P, b.MXS_F64, 0, 0, 0, 0, [1.0], None, ins[k], outs[k])
+          for k in range(npairs)]
+    for p in ps:
+        b.mxs_autotune(p)
+    k = [0]
+
+    def one():
+        b.mxs_compute(ps[k[0] % npairs])
+        k[0] += 1
+
+    sec, _ = time_loop(torch, one, 40, 5)
+    layout = b.mxs_plan_info(ps[0])
+    for p in ps:
+        b.mxs_destroy(p)
+    ident = 2 * 8 * n * n / (sec / 40) / 1e9
+    del ins, outs, u0
     a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
     c = torch.empty_like(a)
     sec, _ = time_loop(torch, lambda: c.copy_(a), 20, 3)
-    gbs = 2 * a.numel() * 8 / (sec / 20) / 1e9
+    tgbs = 2 * a.numel() * 8 / (sec / 20) / 1e9
     del a, c
     torch.cuda.empty_cache()
-    return gbs
+    return {"identity_stencil_gb_per_s": ident, "identity_stencil_layout": layout,
+            "identity_stencil_frac_hbm_peak": ident / HBM_PEAK_GBS, "torch_copy_gb_per_s": tgbs}
 
 
 def cpu_model():
@@ -656,7 +696,8 @@ def main():
         k = args.ch_steps or 500
         extra["ch_ensemble_64"] = bench_ensemble(torch, b, wl, k, min(10, k))
     if "copy" in sections:
-        extra["copy_ceiling_gb_per_s"] = copy_ceiling(torch)
+        log("copy ceiling")
+        extra["copy_ceiling"] = copy_ceiling(torch, b, wl, n)
     result["extra"] = extra
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
