@@ -133,6 +133,10 @@ struct WaveUnit {
 // Every work unit in one launch (one wavefront per unit).
 hipError_t launch_wave_units(int dtype, int bw, const RaggedLines &a, const WaveUnit *units, int nunits,
                              hipStream_t s);
+// Register kernel over the ragged lines of one class nb: sorted positions
+// first .. first + count - 1, one wavefront each.
+hipError_t launch_wave_ragged(int dtype, int bw, int nb, const RaggedLines &a, int first, int count,
+                              hipStream_t s);
 // Register kernel over the rows first .. first + count - 1 (global line
 // indices), each at most 256 nb elements.
 hipError_t launch_wave_rows(int dtype, int bw, int nb, const RowsInst *inst, const int *map, int first,

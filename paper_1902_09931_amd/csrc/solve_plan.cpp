@@ -3,6 +3,7 @@
 #include "solve.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstdio>
 #include <numeric>
 #include <vector>
@@ -100,8 +101,12 @@ struct SolvePlan final : mxs_plan_s {
         hipError_t e = hipSuccess;
         if (geometry == MXS_LINES_RAGGED) {
             if (nlong > 0) e = launch_ragged_lines(dtype, bw, rl, nw, grid, lds, s);
-            if (e == hipSuccess && nunits > 0)
+            if (per_class) {
+                for (size_t q = 0; q < wave.size() && e == hipSuccess; ++q)
+                    e = launch_wave_ragged(dtype, bw, wave[q].nb, rl, wave[q].first, wave[q].count, s);
+            } else if (e == hipSuccess && nunits > 0) {
                 e = launch_wave_units(dtype, bw, rl, static_cast<const WaveUnit *>(units.ptr), nunits, s);
+            }
         } else if (geometry == MXS_LINES_ROWS) {
             const RowsInst *ti = static_cast<const RowsInst *>(tables[cur].ptr);
             if (!wave.empty())
@@ -135,9 +140,35 @@ struct SolvePlan final : mxs_plan_s {
         grid = wave_grid(std::max(1, geometry == MXS_LINES_RAGGED ? nlong : nlines), lds);
     }
 
-    // Wavefronts per line: one (long chunks, few barriers) to four (more
-    // loads in flight per line); chosen by timing.
+    // Ragged lines of at most 4096 elements go out either in one launch
+    // (work-unit table; the kernel holds the registers of the largest class)
+    // or in one launch per length class (each with its own registers).
+    bool per_class = false;
+    double tuned_units = 0, tuned_classes = 0;
+
+    // The form of the ragged register lines, and wavefronts per line of the
+    // LDS kernel: one (long chunks, few barriers) to four (more loads in
+    // flight per line); chosen by timing.
     mxs_status autotune(hipStream_t s) override {
+        auto timed = [&] {
+            return time_launches([&] { return compute(s) == MXS_OK ? hipSuccess : hipErrorLaunchFailure; }, s, 2, 5);
+        };
+        if (geometry == MXS_LINES_RAGGED && nunits > 0 && wave.size() > 1) {
+            double t[2] = {1e30, 1e30};
+            for (int pass = 0; pass < 2; ++pass)
+                for (int f = 0; f < 2; ++f) {
+                    per_class = f == 1;
+                    const double v = timed();
+                    if (v < 0) {
+                        per_class = false;
+                        return fail(MXS_ERR_HIP, "autotune launch failed");
+                    }
+                    t[f] = std::min(t[f], v);
+                }
+            per_class = t[1] < t[0];
+            tuned_units = t[0];
+            tuned_classes = t[1];
+        }
         // only the LDS kernel has a shape to choose
         if (geometry == MXS_LINES_COLS || (geometry == MXS_LINES_RAGGED ? nlong == 0 : !wave.empty()))
             return MXS_OK;
@@ -169,7 +200,11 @@ struct SolvePlan final : mxs_plan_s {
             n += snprintf(buf + n, len - n, " lds_kernel_lines=%d waves_per_line=%d grid=%d lds=%zu",
                           geometry == MXS_LINES_RAGGED ? nlong : nlines, nw, grid, lds);
         if (geometry == MXS_LINES_RAGGED && nunits > 0 && n < len)
-            n += snprintf(buf + n, len - n, " launches=%d units=%d", (nlong > 0) + 1, nunits);
+            n += snprintf(buf + n, len - n, " form=%s launches=%d units=%d", per_class ? "classes" : "units",
+                          (nlong > 0) + (per_class ? static_cast<int>(wave.size()) : 1), nunits);
+        if (tuned_units > 0 && n < len)
+            n += snprintf(buf + n, len - n, " tuned_us_units=%.1f tuned_us_classes=%.1f", tuned_units * 1e6,
+                          tuned_classes * 1e6);
         for (size_t q = 0; q < wave.size() && n < len; ++q)
             n += snprintf(buf + n, len - n, " register_kernel(nb=%d lines=%d)", wave[q].nb, wave[q].count);
     }
@@ -283,6 +318,8 @@ extern "C" mxs_status mxs_create_cyclic_solve(int bw, const double *coef, int ge
                 units.push_back({w.first + q, std::min(per, w.count - q), w.nb, 0});
         }
         p->nunits = static_cast<int>(units.size());
+        // MXS_RAGGED_FORM=classes starts the plan with one launch per class
+        if (const char *env = getenv("MXS_RAGGED_FORM")) p->per_class = env[0] == 'c';
         if (!units.empty() &&
             (e = p->units.upload(units.data(), sizeof(WaveUnit) * units.size())) != hipSuccess) {
             delete p;

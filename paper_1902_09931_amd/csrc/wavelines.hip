@@ -121,6 +121,17 @@ __global__ void __launch_bounds__(64) wave_units_kernel(const RaggedLines a,
     }
 }
 
+// One ragged line of class NB per wavefront (positions first .. first +
+// count - 1 of the sorted order): one launch per class, each with the
+// registers of its own class.
+template <typename T, int BW, int NB>
+__global__ void __launch_bounds__(64) wave_ragged_kernel(const RaggedLines a, int first, int count) {
+    __shared__ __align__(16) T stage[Stage<T, WaveShape<NB>::E>::SIZE];
+    const int k = blockIdx.x;
+    if (k >= count) return;
+    wave_line<T, BW, NB>(RaggedSrc<T>{a}, first + k, stage);
+}
+
 template <typename T, int BW, int NB>
 __global__ void __launch_bounds__(64) wave_rows_kernel(const RowsInst *__restrict__ inst,
                                                        const int *__restrict__ map, int first,
@@ -138,6 +149,20 @@ hipError_t units_bw(int bw, const RaggedLines &a, const WaveUnit *units, int nun
         hipLaunchKernelGGL((wave_units_kernel<T, 2>), grid, block, 0, s, a, units, nunits);
     else
         hipLaunchKernelGGL((wave_units_kernel<T, 1>), grid, block, 0, s, a, units, nunits);
+    return hipGetLastError();
+}
+
+template <typename T, int BW>
+hipError_t ragged_nb(int nb, const RaggedLines &a, int first, int count, hipStream_t s) {
+    const dim3 grid(count), block(64);
+    switch (nb) {
+    case 1: hipLaunchKernelGGL((wave_ragged_kernel<T, BW, 1>), grid, block, 0, s, a, first, count); break;
+    case 2: hipLaunchKernelGGL((wave_ragged_kernel<T, BW, 2>), grid, block, 0, s, a, first, count); break;
+    case 4: hipLaunchKernelGGL((wave_ragged_kernel<T, BW, 4>), grid, block, 0, s, a, first, count); break;
+    case 8: hipLaunchKernelGGL((wave_ragged_kernel<T, BW, 8>), grid, block, 0, s, a, first, count); break;
+    case 16: hipLaunchKernelGGL((wave_ragged_kernel<T, BW, 16>), grid, block, 0, s, a, first, count); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -172,6 +197,18 @@ hipError_t launch_wave_units(int dtype, int bw, const RaggedLines &a, const Wave
     case F64: return units_bw<double>(bw, a, units, nunits, s);
     case F32: return units_bw<float>(bw, a, units, nunits, s);
     case BF16: return units_bw<bf16>(bw, a, units, nunits, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_wave_ragged(int dtype, int bw, int nb, const RaggedLines &a, int first, int count,
+                              hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    if (bw != 1 && bw != 2) return hipErrorInvalidValue;
+    switch (dtype) {
+    case F64: return bw == 2 ? ragged_nb<double, 2>(nb, a, first, count, s) : ragged_nb<double, 1>(nb, a, first, count, s);
+    case F32: return bw == 2 ? ragged_nb<float, 2>(nb, a, first, count, s) : ragged_nb<float, 1>(nb, a, first, count, s);
+    case BF16: return bw == 2 ? ragged_nb<bf16, 2>(nb, a, first, count, s) : ragged_nb<bf16, 1>(nb, a, first, count, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -91,10 +91,13 @@ def test_grid_lines_reduced_storage_in_place_and_pitch(dt, geometry):
     check(to_host(buf, nx), ref, dt)
 
 
+@pytest.mark.parametrize("form", ["units", "classes"])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-def test_full_batch_tridiagonal(dt):
+def test_full_batch_tridiagonal(monkeypatch, dt, form):
     """65536 periodic lines, lengths U{64..4096}, circ(-1, 2.5, -1): every
-    output against the oracle."""
+    output against the oracle, in one launch (work units) and in one launch
+    per length class."""
+    monkeypatch.setenv("MXS_RAGGED_FORM", form)
     lengths, offs = wl.ragged_lengths()
     r = np.random.default_rng(5).uniform(-1, 1, int(offs[-1]))
     rr = round_to(r, dt)
@@ -177,12 +180,17 @@ CLASS_LENGTHS = [5, 6, 7, 63, 64, 65, 255, 256, 257, 259, 511, 512, 513, 1000, 1
                  2047, 2048, 2049, 3001, 4093, 4095, 4096, 4097, 6000, 9001]
 
 
-@pytest.mark.parametrize("kernel", ["register", "lds"])
+@pytest.mark.parametrize("kernel", ["register", "classes", "lds"])
 @pytest.mark.parametrize("coef", [TRI, PENTA, OTHER])
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
 def test_line_kernels_every_length_class(monkeypatch, kernel, coef, dt):
+    """Every register class with partial lanes, and lines for the LDS kernel:
+    the register lines in one launch of work units, in one launch per class,
+    or every line in the LDS kernel."""
     if kernel == "lds":
         monkeypatch.setenv("MXS_LINE_KERNEL", "lds")
+    if kernel == "classes":
+        monkeypatch.setenv("MXS_RAGGED_FORM", "classes")
     bw = len(coef) - 1
     rng = np.random.default_rng(41 + bw)
     lengths = rng.permutation(CLASS_LENGTHS)
@@ -199,6 +207,7 @@ def test_line_kernels_every_length_class(monkeypatch, kernel, coef, dt):
         for nb in (1, 2, 4, 8, 16):
             assert f"register_kernel(nb={nb}" in info
         assert "lds_kernel_lines=3 " in info     # 4097, 6000 and 9001
+        assert ("form=classes launches=6 " if kernel == "classes" else "form=units launches=2 ") in info
     b.mxs_compute(p)
     torch.cuda.synchronize()
     b.mxs_destroy(p)
@@ -222,6 +231,24 @@ def test_row_kernels(monkeypatch, kernel, nx):
     torch.cuda.synchronize()
     b.mxs_destroy(p)
     check(to_host(dx), oracle.cyclic_solve_grid(oracle.circulant_bands(PENTA_SMALL), 1, r), "f64")
+
+
+def test_ragged_autotune_times_both_forms():
+    lengths, offs = wl.ragged_lengths(nbatch=4000, seed=15)
+    r = np.random.default_rng(16).uniform(-1, 1, int(offs[-1]))
+    drhs = to_device(r, "f32")
+    dx = torch.empty_like(drhs)
+    p = b.mxs_create_cyclic_solve(1, TRI, b.MXS_LINES_RAGGED, 0, 0, 0, offs, b.MXS_F32, drhs, dx)
+    try:
+        b.mxs_autotune(p)
+        info = b.mxs_plan_info(p)
+        assert "tuned_us_units=" in info and "tuned_us_classes=" in info
+        b.mxs_compute(p)
+        torch.cuda.synchronize()
+    finally:
+        b.mxs_destroy(p)
+    check(dx.double().cpu().numpy(),
+          oracle.cyclic_solve_batch(oracle.circulant_bands(TRI), offs, round_to(r, "f32")), "f32")
 
 
 def test_ragged_solve_is_one_launch_and_graph_capturable():
