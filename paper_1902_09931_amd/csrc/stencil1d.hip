@@ -9,9 +9,10 @@
 // values (plus an x halo of PAD elements each side) and the slice of signal
 // offsets that meets the tile in LDS, requesting all three at once.  Each
 // vector of outputs finds its signal by binary search in that slice.
-// Outputs whose window stays inside their signal read LDS directly; the few
-// near a signal end wrap within the signal (periodic) and read the wrapped
-// value from LDS when it is staged, else from global memory.
+// Outputs whose window stays inside their signal read LDS directly (a
+// vector whose elements all do takes a straight-line path); the few near a
+// signal end wrap within the signal (periodic) and read the wrapped value
+// from LDS when it is staged, else from global memory.
 #include "mxs_internal.h"
 
 namespace mxs {
@@ -103,6 +104,24 @@ __global__ void __launch_bounds__(256) stencil1d_kernel(const Stencil1DArgs a) {
             }
         }
         long long sb = soff[lo], se = soff[lo + 1];
+        // the common case: the whole vector lies in one signal with every
+        // window inside it (no wrap, every output written): straight-line
+        // FMAs over the staged values
+        if (a.vec_ok && eb >= sb + a.L && eb + V - 1 + a.R <= se - 1) {
+            const A *lp = lds + PAD + (eb - e0) - a.L;
+            A x[V + NWX - 1];
+#pragma unroll
+            for (int k = 0; k < V + NWX - 1; ++k) x[k] = lp[k];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                A acc = A(0);
+#pragma unroll
+                for (int p = 0; p < NWX; ++p) acc = fma(w[p], x[v + p], acc);
+                res[v] = acc;
+            }
+            store_vec_nt<T>(out + eb, res);
+            continue;
+        }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const long long e = eb + v;
