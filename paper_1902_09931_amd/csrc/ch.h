@@ -26,7 +26,8 @@ struct RhsInst {
 };
 
 // Threads per workgroup of the right-hand side: at most kRhsThreads, at
-// least kRhsThreadsMin (a multiple of 64); a strip is threads * V columns.
+// least kRhsThreadsMin (a multiple of 64); a strip is threads * V columns,
+// V = 16 bytes of state per thread (2 doubles, 4 floats, 8 bfloat16s).
 constexpr int kRhsThreads = 256;
 constexpr int kRhsThreadsMin = 64;
 

@@ -74,11 +74,8 @@ __global__ void __launch_bounds__(kMassThreads) mass_final_kernel(const MassInst
 
 template <typename T, typename TW>
 hipError_t rhs_one(const RhsInst *inst, const int *map, int blocks, int threads, hipStream_t s) {
-    using A = typename St<T>::acc;
-    constexpr int V = St<T>::V;
-    constexpr int PAD = V >= 2 ? V : 2;
     if (threads < kRhsThreadsMin || threads > kRhsThreads || threads % 64) return hipErrorInvalidValue;
-    const size_t lds = 2 * 4 * static_cast<size_t>(PAD + threads * V + PAD) * sizeof(A);
+    const size_t lds = rhs_lds_bytes<T>(threads);
     hipLaunchKernelGGL((ch_rhs_kernel<T, TW>), dim3(blocks), dim3(threads), lds, s, inst, map);
     return hipGetLastError();
 }

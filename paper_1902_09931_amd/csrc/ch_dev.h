@@ -5,8 +5,43 @@
 
 #include "ch.h"
 
+#include <type_traits>
+
 namespace mxs {
 namespace {
+
+// Elements per thread and strip column group of the right-hand side: one
+// 16-byte vector of the state per thread (2 doubles, 4 floats, 8 bfloat16s).
+template <typename T> struct RhsVec { static constexpr int V = 16 / static_cast<int>(sizeof(T)); };
+
+// V consecutive state values from a 16-byte aligned address, as floats or
+// doubles.
+template <typename T, int V>
+__device__ __forceinline__ void rhs_load(gptr<const T> p, typename St<T>::acc *x) {
+    if constexpr (std::is_same<T, bf16>::value) {
+        const v4u_t v = *reinterpret_cast<gptr<const v4u_t>>(p);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            x[2 * k] = __uint_as_float(w[k] << 16);
+            x[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+        }
+    } else {
+        load_vec<T>(p, x);
+    }
+}
+
+// V values of R (float or double) with streaming stores, 16 bytes at a time.
+template <typename TW, int V>
+__device__ __forceinline__ void rhs_store(gptr<TW> p, const TW *x) {
+    constexpr int W = St<TW>::V;
+#pragma unroll
+    for (int k = 0; k < V; k += W) store_vec_nt<TW>(p + k, x + k);
+}
+
+// Input rows per stage: 4, or 2 for bfloat16, whose 8 values per thread and
+// row would otherwise hold too many registers for the double-buffered loads.
+template <typename T> constexpr int kRhsStage = sizeof(T) == 2 ? 2 : 4;
 
 template <typename A> __device__ __forceinline__ A wb_of(const RhsInst &I, int k);
 template <> __device__ __forceinline__ double wb_of<double>(const RhsInst &I, int k) { return I.wb[k]; }
@@ -31,9 +66,9 @@ constexpr bool lap_tap(int q, int p) { return q == 1 || p == 1; }
 template <typename T, typename TW>
 __device__ __forceinline__ void rhs_tile(const RhsInst &I, const int local, unsigned char *smem) {
     using A = typename St<T>::acc;
-    constexpr int V = St<T>::V;
+    constexpr int V = RhsVec<T>::V;
     constexpr int PAD = V >= 2 ? V : 2;   // two halo columns, rounded up to a vector
-    constexpr int G = 4;
+    constexpr int G = kRhsStage<T>;       // input rows per stage
     constexpr int XB = V + 4;             // biharmonic window per thread
     constexpr int XL = V + 2;             // Laplacian window per thread
 
@@ -88,8 +123,8 @@ __device__ __forceinline__ void rhs_tile(const RhsInst &I, const int local, unsi
             const gptr<const T> cr = cur + static_cast<long long>(r) * nx;
             const gptr<const T> pr = prev + static_cast<long long>(r) * nx;
             if (full_vec) {
-                load_vec<T>(cr + ib, c[u]);
-                load_vec<T>(pr + ib, p[u]);
+                rhs_load<T, V>(cr + ib, c[u]);
+                rhs_load<T, V>(pr + ib, p[u]);
             } else {
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
@@ -188,7 +223,7 @@ __device__ __forceinline__ void rhs_tile(const RhsInst &I, const int local, unsi
                 if (jj >= 0 && jj < H) {
                     const gptr<TW> rowp = R + static_cast<long long>(up ? j0 + H - 1 - jj : j0 + jj) * nx;
                     if (full_vec) {
-                        store_vec_nt<TW>(rowp + ib, acc[0]);
+                        rhs_store<TW, V>(rowp + ib, acc[0]);
                     } else {
 #pragma unroll
                         for (int v = 0; v < V; ++v)
@@ -220,7 +255,7 @@ __device__ __forceinline__ void rhs_tile(const RhsInst &I, const int local, unsi
 
 // Bytes of LDS the right-hand side of a workgroup of `threads` threads uses.
 template <typename T> constexpr size_t rhs_lds_bytes(int threads) {
-    return 2 * 4 * static_cast<size_t>((St<T>::V >= 2 ? St<T>::V : 2) * 2 + threads * St<T>::V) *
+    return 2 * kRhsStage<T> * static_cast<size_t>((RhsVec<T>::V >= 2 ? RhsVec<T>::V : 2) * 2 + threads * RhsVec<T>::V) *
            sizeof(typename St<T>::acc);
 }
 

@@ -86,6 +86,7 @@ struct CHPlan final : mxs_plan_s {
     std::vector<RowRange> row_ranges;
     DevBuf partial, mass_out;
     double *mass_host = nullptr;
+    int bgroups = 16;   // phase B threads per column
     int rhs_blocks = 0, rhs_rows = 16, rhs_threads = kRhsThreads, row_lines = 0, row_grid = 1, row_nw = 1, colsAC = 0, colsB = 0,
         mass_blocks = 0, max_nx = 0;
     size_t row_lds = 0;
@@ -148,6 +149,7 @@ struct CHPlan final : mxs_plan_s {
             pa.colsB_map = map_of(colsB_map);
             pa.colsAC = colsAC;
             pa.colsB = colsB;
+            pa.bgroups = bgroups;
             pa.bar = static_cast<unsigned *>(bar.ptr);
             pa.spin_limit = spin_limit;
             pa.stage_bytes = static_cast<int>(persist_stage_bytes(dtype, persist_nbmax));
@@ -164,7 +166,7 @@ struct CHPlan final : mxs_plan_s {
                                  row_ranges[q].count, s);
         if (e != hipSuccess) return e;
         return launch_cols(wdtype, dtype, 2, 1, static_cast<const ColsInst *>(cols_d[r].ptr),
-                           map_of(colsAC_map), map_of(colsB_map), colsAC, colsB, s);
+                           map_of(colsAC_map), map_of(colsB_map), colsAC, colsB, bgroups, s);
     }
 
     hipError_t capture(int r) {
@@ -293,7 +295,7 @@ struct CHPlan final : mxs_plan_s {
     mxs_status build_rhs(int rows) {
         const int n = ninst();
         const int cus = device_cu_count();
-        const int Vs = dtype == F64 ? 2 : 4;
+        const int Vs = 16 / dtype_size(dtype);   // state elements per thread (one 16-byte vector)
         auto tiles = [&](int r) {
             long long t = 0;
             for (const Inst &I : inst)
@@ -432,9 +434,9 @@ struct CHPlan final : mxs_plan_s {
     void info(char *buf, int len) const override {
         const int launches = persistent ? 1 : 1 + (row_ranges.empty() ? 1 : static_cast<int>(row_ranges.size())) + 3;
         int n = snprintf(buf, len, "ch instances=%d dtype=%d step=%s launches_per_step=%d rhs_rows=%d rhs_threads=%d "
-                         "rhs_blocks=%d cols_blocks=%d",
+                         "rhs_blocks=%d cols_blocks=%d colsB_groups=%d",
                          ninst(), dtype, persistent ? "persistent" : "separate", launches, rhs_rows, rhs_threads,
-                         rhs_blocks, colsAC);
+                         rhs_blocks, colsAC, bgroups);
         if (persistent && n < len)
             n += snprintf(buf + n, len - n, " persist_grid=%d persist_graph=%d", persist_grid, persist_nograph ? 0 : 1);
         if (best_persist && n < len)
@@ -460,6 +462,13 @@ struct CHPlan final : mxs_plan_s {
         const bool reg_rows = maxnx <= kWaveLineMax && !force_lds_lines();
         std::vector<double> pt(static_cast<size_t>(4) * kPowEntries * n);
         int bAC = 0, bB = 0;
+        {
+            // phase B threads per column from the mean number of segments
+            long long segs = 0;
+            for (const Inst &I : inst) segs += (I.ny + kSeg - 1) / kSeg;
+            bgroups = cols_b_groups(static_cast<int>(segs / n));
+        }
+        const int bcols = cols_b_cols(bgroups);
         for (int g = 0; g < n; ++g) {
             Inst &I = inst[g];
             const double a = 2.0 / 3.0 * D * gamma * I.dt;
@@ -490,7 +499,7 @@ struct CHPlan final : mxs_plan_s {
             co.blk0 = bAC;
             co.blkB0 = bB;
             bAC += co.nstrips * co.nseg;
-            bB += (I.nx + kBCols - 1) / kBCols;
+            bB += (I.nx + bcols - 1) / bcols;
             hipError_t e = I.carry.alloc(sizeof(double) * 4 * static_cast<size_t>(I.nx) * co.nseg);
             if (e != hipSuccess) return hip_fail(e, "carry allocation");
             co.carry = static_cast<double *>(I.carry.ptr);
@@ -562,7 +571,7 @@ struct CHPlan final : mxs_plan_s {
             std::vector<int> ac(n), bb(n), mbk(n);
             for (int g = 0; g < n; ++g) {
                 ac[g] = cols_h[0][g].nstrips * cols_h[0][g].nseg;
-                bb[g] = (inst[g].nx + kBCols - 1) / kBCols;
+                bb[g] = (inst[g].nx + bcols - 1) / bcols;
                 mbk[g] = mass_h[0][g].nblk;
             }
             std::vector<int> line_inst(row_lines);

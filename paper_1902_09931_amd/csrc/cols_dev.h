@@ -142,8 +142,8 @@ __device__ __forceinline__ void cols_a_block(const ColsInst *__restrict__ inst, 
     cy[3 * I.nx] = t1;
 }
 
-// Phase B: the segments of a column are split into kBGroups groups, one
-// thread each (a workgroup covers kBCols columns).  Each thread composes the
+// Phase B: the segments of a column are split into G groups, one thread
+// each (a workgroup covers kColsThreads / G columns).  Each thread composes the
 // affine maps of its segments, the groups of a column combine their maps
 // through LDS (wrap-around closure included), and each thread then writes
 // the true incoming states of its own segments.  Summaries are loaded PB
@@ -154,9 +154,10 @@ __device__ __forceinline__ void mat2_load(const double *m, Aff &x) {
     x.a = m[0]; x.b = m[1]; x.c = m[2]; x.d = m[3];
 }
 
-template <int BW>
+template <int BW, int G>
 __device__ __forceinline__ void cols_b_block(const ColsInst *__restrict__ inst, const int *__restrict__ map,
-                                             const int blk, Aff (*xa)[kBCols]) {
+                                             const int blk, Aff *xa) {
+    constexpr int kBCols = kColsThreads / G;
     const int g = find_inst(map, blk);
     const ColsInst &I = inst[g];
     const int cl = threadIdx.x % kBCols, q = threadIdx.x / kBCols;
@@ -165,7 +166,7 @@ __device__ __forceinline__ void cols_b_block(const ColsInst *__restrict__ inst, 
     const long long nx = I.nx;
     const gptr<double> cy = as_global(I.carry) + (valid ? col : 0);
     const int ns = I.nseg;
-    const int sp = (ns + kBGroups - 1) / kBGroups;
+    const int sp = (ns + G - 1) / G;
     const int sb = min(q * sp, ns), se = min(sb + sp, ns);
     Aff Tf, Tl, Qf, Ql;
     mat2_load(I.Tf, Tf);
@@ -194,12 +195,12 @@ __device__ __forceinline__ void cols_b_block(const ColsInst *__restrict__ inst, 
                 }
         }
     }
-    xa[q][cl] = m;
+    xa[q * kBCols + cl] = m;
     __syncthreads();
     Aff pre = aff_identity(), tot = aff_identity();
 #pragma unroll
-    for (int r = 0; r < kBGroups; ++r) {
-        const Aff x = xa[r][cl];
+    for (int r = 0; r < G; ++r) {
+        const Aff x = xa[r * kBCols + cl];
         if (r < q) pre = compose(x, pre);
         tot = compose(x, tot);
     }
@@ -260,13 +261,13 @@ __device__ __forceinline__ void cols_b_block(const ColsInst *__restrict__ inst, 
             }
         }
     }
-    xa[q][cl] = m;
+    xa[q * kBCols + cl] = m;
     __syncthreads();
     pre = aff_identity();
     tot = aff_identity();
 #pragma unroll
-    for (int r = kBGroups - 1; r >= 0; --r) {
-        const Aff x = xa[r][cl];
+    for (int r = G - 1; r >= 0; --r) {
+        const Aff x = xa[r * kBCols + cl];
         if (r > q) pre = compose(x, pre);
         tot = compose(x, tot);
     }

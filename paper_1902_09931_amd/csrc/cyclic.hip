@@ -194,11 +194,11 @@ __global__ void __launch_bounds__(kColsThreads) cols_phase_a(const ColsInst *__r
     cols_a_block<TR, BW>(inst, map, blockIdx.x);
 }
 
-template <int BW>
+template <int BW, int G>
 __global__ void __launch_bounds__(kColsThreads) cols_phase_b(const ColsInst *__restrict__ inst,
                                                             const int *__restrict__ map) {
-    __shared__ Aff xa[kBGroups][kBCols];
-    cols_b_block<BW>(inst, map, blockIdx.x, xa);
+    __shared__ Aff xa[kColsThreads];
+    cols_b_block<BW, G>(inst, map, blockIdx.x, xa);
 }
 
 template <typename TR, typename TX, int BW, int EPI>
@@ -233,9 +233,14 @@ hipError_t rows_one(const RowsInst *inst, const int *map, int nlines, int nw, in
 
 template <typename TR, typename TX, int BW, int EPI>
 hipError_t cols_one(const ColsInst *inst, const int *mapAC, const int *mapB, int blocksAC,
-                    int blocksB, hipStream_t s) {
+                    int blocksB, int bgroups, hipStream_t s) {
     hipLaunchKernelGGL((cols_phase_a<TR, BW>), dim3(blocksAC), dim3(kColsThreads), 0, s, inst, mapAC);
-    hipLaunchKernelGGL((cols_phase_b<BW>), dim3(blocksB), dim3(kColsThreads), 0, s, inst, mapB);
+    if (bgroups == 16)
+        hipLaunchKernelGGL((cols_phase_b<BW, 16>), dim3(blocksB), dim3(kColsThreads), 0, s, inst, mapB);
+    else if (bgroups == 4)
+        hipLaunchKernelGGL((cols_phase_b<BW, 4>), dim3(blocksB), dim3(kColsThreads), 0, s, inst, mapB);
+    else
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL((cols_phase_c<TR, TX, BW, EPI>), dim3(blocksAC), dim3(kColsThreads), 0, s,
                        inst, mapAC);
     return hipGetLastError();
@@ -243,9 +248,9 @@ hipError_t cols_one(const ColsInst *inst, const int *mapAC, const int *mapB, int
 
 template <typename TR, typename TX, int EPI>
 hipError_t cols_bw(int bw, const ColsInst *inst, const int *mapAC, const int *mapB, int blocksAC,
-                   int blocksB, hipStream_t s) {
-    return bw == 1 ? cols_one<TR, TX, 1, EPI>(inst, mapAC, mapB, blocksAC, blocksB, s)
-                   : cols_one<TR, TX, 2, EPI>(inst, mapAC, mapB, blocksAC, blocksB, s);
+                   int blocksB, int bgroups, hipStream_t s) {
+    return bw == 1 ? cols_one<TR, TX, 1, EPI>(inst, mapAC, mapB, blocksAC, blocksB, bgroups, s)
+                   : cols_one<TR, TX, 2, EPI>(inst, mapAC, mapB, blocksAC, blocksB, bgroups, s);
 }
 
 }  // namespace
@@ -277,16 +282,17 @@ hipError_t launch_rows(int dtype, int bw, const RowsInst *inst, const int *map, 
 }
 
 hipError_t launch_cols(int rhs_dtype, int x_dtype, int bw, int epilogue, const ColsInst *inst,
-                       const int *mapAC, const int *mapB, int blocksAC, int blocksB, hipStream_t s) {
+                       const int *mapAC, const int *mapB, int blocksAC, int blocksB, int bgroups,
+                       hipStream_t s) {
     if (bw != 1 && bw != 2) return hipErrorInvalidValue;
     if (epilogue == 0) {
-        if (rhs_dtype == F64 && x_dtype == F64) return cols_bw<double, double, 0>(bw, inst, mapAC, mapB, blocksAC, blocksB, s);
-        if (rhs_dtype == F32 && x_dtype == F32) return cols_bw<float, float, 0>(bw, inst, mapAC, mapB, blocksAC, blocksB, s);
-        if (rhs_dtype == BF16 && x_dtype == BF16) return cols_bw<bf16, bf16, 0>(bw, inst, mapAC, mapB, blocksAC, blocksB, s);
+        if (rhs_dtype == F64 && x_dtype == F64) return cols_bw<double, double, 0>(bw, inst, mapAC, mapB, blocksAC, blocksB, bgroups, s);
+        if (rhs_dtype == F32 && x_dtype == F32) return cols_bw<float, float, 0>(bw, inst, mapAC, mapB, blocksAC, blocksB, bgroups, s);
+        if (rhs_dtype == BF16 && x_dtype == BF16) return cols_bw<bf16, bf16, 0>(bw, inst, mapAC, mapB, blocksAC, blocksB, bgroups, s);
     } else if (bw == 2) {
-        if (rhs_dtype == F64 && x_dtype == F64) return cols_one<double, double, 2, 1>(inst, mapAC, mapB, blocksAC, blocksB, s);
-        if (rhs_dtype == F32 && x_dtype == F32) return cols_one<float, float, 2, 1>(inst, mapAC, mapB, blocksAC, blocksB, s);
-        if (rhs_dtype == F32 && x_dtype == BF16) return cols_one<float, bf16, 2, 1>(inst, mapAC, mapB, blocksAC, blocksB, s);
+        if (rhs_dtype == F64 && x_dtype == F64) return cols_one<double, double, 2, 1>(inst, mapAC, mapB, blocksAC, blocksB, bgroups, s);
+        if (rhs_dtype == F32 && x_dtype == F32) return cols_one<float, float, 2, 1>(inst, mapAC, mapB, blocksAC, blocksB, bgroups, s);
+        if (rhs_dtype == F32 && x_dtype == BF16) return cols_one<float, bf16, 2, 1>(inst, mapAC, mapB, blocksAC, blocksB, bgroups, s);
     }
     return hipErrorInvalidValue;
 }

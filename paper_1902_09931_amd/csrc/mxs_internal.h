@@ -99,6 +99,7 @@ __device__ __forceinline__ void store_vec<bf16>(bf16 *p, const float *x) {
 typedef double v2d_t __attribute__((ext_vector_type(2)));
 typedef float v4f_t __attribute__((ext_vector_type(4)));
 typedef unsigned int v2u_t __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u_t __attribute__((ext_vector_type(4)));
 template <typename T>
 __device__ __forceinline__ void store_vec_nt(T *p, const typename St<T>::acc *x);
 template <>

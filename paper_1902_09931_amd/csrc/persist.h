@@ -19,6 +19,7 @@ struct PersistArgs {
     const ColsInst *cols;        // column phases
     const int *colsAC_map, *colsB_map;
     int colsAC, colsB;
+    int bgroups;                 // phase B threads per column (4 or 16)
     unsigned *bar;               // device words: arrivals, generation, exits, error
     int spin_limit;              // polls of a barrier wait before it fails
     int stage_bytes;             // LDS stage of one wavefront in the row phase

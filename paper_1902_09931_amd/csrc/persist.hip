@@ -114,9 +114,10 @@ __global__ void __launch_bounds__(kPersistThreads, 2) ch_step_persistent(const P
 
     // 4. column phase B: carries between segments
     if (good) {
-        Aff(*xa)[kBCols] = reinterpret_cast<Aff(*)[kBCols]>(lds);
+        Aff *xa = reinterpret_cast<Aff *>(lds);
         for (int b = blockIdx.x; b < p.colsB; b += G) {
-            cols_b_block<2>(p.cols, p.colsB_map, b, xa);
+            if (p.bgroups == 16) cols_b_block<2, 16>(p.cols, p.colsB_map, b, xa);
+            else cols_b_block<2, 4>(p.cols, p.colsB_map, b, xa);
             __syncthreads();
         }
         good = grid_sync(p.bar, p.spin_limit, ok);
@@ -169,7 +170,7 @@ size_t persist_lds_bytes(int dtype, int nbmax) {
                                     : dtype == F32 ? rhs_lds_bytes<float>(kPersistThreads)
                                                    : rhs_lds_bytes<bf16>(kPersistThreads);
     const size_t rows = (kPersistThreads / 64) * persist_stage_bytes(dtype, nbmax);
-    const size_t colsb = sizeof(Aff) * kBGroups * kBCols;
+    const size_t colsb = sizeof(Aff) * kColsThreads;
     return 16 + std::max(rhs, std::max(rows, colsb));
 }
 

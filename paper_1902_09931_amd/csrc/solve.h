@@ -91,9 +91,12 @@ struct RowsInst {
 // --- columns: three phases over segments of kSeg rows -------------------------
 constexpr int kSeg = 32;
 constexpr int kColsThreads = 256;
-// phase B: kBGroups threads per column, kBCols columns per workgroup
-constexpr int kBGroups = 16;
-constexpr int kBCols = kColsThreads / kBGroups;
+// phase B: G threads per column (G = 4 or 16), kColsThreads / G columns per
+// workgroup.  Each thread composes the maps of its share of a column's
+// segments and then combines the G shares, so G trades the serial chain per
+// thread against the combine: 16 for long columns, 4 for short ones.
+inline int cols_b_groups(int nseg) { return nseg >= 64 ? 16 : 4; }
+inline int cols_b_cols(int groups) { return kColsThreads / groups; }
 
 struct ColsInst {
     const void *rhs;            // rhs dtype
@@ -144,6 +147,7 @@ hipError_t launch_wave_rows(int dtype, int bw, int nb, const RowsInst *inst, con
 // epilogue: 0 = x = A^-1 rhs; 1 = Cahn-Hilliard update x = 2 cur - prev + A^-1 rhs.
 // (rhs dtype, output dtype) pairs: (F64,F64), (F32,F32), (BF16,BF16), (F32,BF16).
 hipError_t launch_cols(int rhs_dtype, int x_dtype, int bw, int epilogue, const ColsInst *inst,
-                       const int *mapAC, const int *mapB, int blocksAC, int blocksB, hipStream_t s);
+                       const int *mapAC, const int *mapB, int blocksAC, int blocksB, int bgroups,
+                       hipStream_t s);
 
 }  // namespace mxs

@@ -52,7 +52,7 @@ struct SolvePlan final : mxs_plan_s {
     std::vector<WaveRange> wave;
     int nunits = 0;
     int nlong = 0;
-    int nlines = 0, grid = 1, blocksAC = 0, blocksB = 0, nw = 1;
+    int nlines = 0, grid = 1, blocksAC = 0, blocksB = 0, nw = 1, bgroups = 16;
     size_t lds = 0, bytes = 0;
     SolvePlan() : mxs_plan_s(KIND_SOLVE) {}
 
@@ -115,7 +115,7 @@ struct SolvePlan final : mxs_plan_s {
                 e = launch_rows(dtype, bw, ti, nullptr, nlines, nw, grid, lds, s);
         } else {
             e = launch_cols(dtype, dtype, bw, 0, static_cast<const ColsInst *>(tables[cur].ptr), nullptr,
-                            nullptr, blocksAC, blocksB, s);
+                            nullptr, blocksAC, blocksB, bgroups, s);
         }
         return e == hipSuccess ? MXS_OK : hip_fail(e, "cyclic solve launch");
     }
@@ -366,7 +366,8 @@ extern "C" mxs_status mxs_create_cyclic_solve(int bw, const double *coef, int ge
             p->cols.blk0 = 0;
             p->cols.blkB0 = 0;
             p->blocksAC = p->cols.nstrips * p->cols.nseg;
-            p->blocksB = (nx + kBCols - 1) / kBCols;
+            p->bgroups = cols_b_groups((ny + kSeg - 1) / kSeg);
+            p->blocksB = (nx + cols_b_cols(p->bgroups) - 1) / cols_b_cols(p->bgroups);
             e = p->carry.alloc(sizeof(double) * 4 * static_cast<size_t>(nx) * p->cols.nseg);
             p->cols.carry = static_cast<double *>(p->carry.ptr);
         }

@@ -668,7 +668,6 @@ hipError_t dispatch(int nwx, int nwy, const Stencil2DArgs &a, int threads, hipSt
 // unless its words XOR to a fixed value (then one word of the same buffer,
 // which only serves this kernel): the loads replace the contents of the
 // memory-side cache with clean lines.
-typedef unsigned int v4u_t __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256) cache_flush_kernel(void *buf, size_t n16) {
     const gptr<const v4u_t> p = as_global(static_cast<const v4u_t *>(buf));
     uint32_t x = 0;
