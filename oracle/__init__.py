@@ -59,6 +59,8 @@ def lib():
         L.orc_ch_run_stored.argtypes = [_ll, _ll, _dbl, _dbl, _dbl, _dbl, _dbl, _int, _int, _ll,
                                         _f64p, _f64p]
         L.orc_round_storage.argtypes = [_f64p, _f64p, _ll, _int]
+        L.orc_ch_run_nudged.argtypes = [_ll, _ll, _dbl, _dbl, _dbl, _dbl, _dbl, _int, _ll,
+                                        ctypes.c_ulonglong, _f64p, _f64p]
         L.orc_weno_adv.argtypes = [_f64p, _f64p, _f64p, _f64p, _ll, _ll, _ll, _dbl, _dbl]
         L.orc_weno_derivatives.argtypes = [_f64p, _f64p, _f64p, _f64p, _f64p, _ll, _ll, _ll,
                                            _dbl, _dbl]
@@ -67,7 +69,8 @@ def lib():
         for name in ("orc_stencil2d", "orc_stencil2d_at", "orc_stencil1d_batch",
                      "orc_cyclic_solve_batch", "orc_cyclic_solve_grid", "orc_ch_step",
                      "orc_ch_run", "orc_ch_step_stored", "orc_ch_run_stored",
-                     "orc_round_storage", "orc_weno_adv", "orc_weno_derivatives"):
+                     "orc_round_storage", "orc_weno_adv", "orc_weno_derivatives",
+                     "orc_ch_run_nudged"):
             getattr(L, name).restype = _int
         _lib = L
     return _lib
@@ -197,6 +200,18 @@ def ch_run(c_prev, c_cur, nsteps, dx, dy, dt, D=1.0, gamma=0.01, nonlinear=True)
     ny, nx = cc.shape
     _check(lib().orc_ch_run(nx, ny, dx, dy, dt, D, gamma, int(bool(nonlinear)),
                             int(nsteps), cp, cc), "ch_run")
+    return cp, cc
+
+
+def ch_run_nudged(c_prev, c_cur, nsteps, dx, dy, dt, seed, D=1.0, gamma=0.01, nonlinear=True):
+    """ch_run with every window weight and band value of the step moved by
+    one ulp, up or down by a seeded sequence (seed != 0): another equally
+    valid double rounding of the scheme's coefficients."""
+    cp = _f64(c_prev).copy()
+    cc = _f64(c_cur).copy()
+    ny, nx = cc.shape
+    _check(lib().orc_ch_run_nudged(nx, ny, dx, dy, dt, D, gamma, int(bool(nonlinear)),
+                                   int(nsteps), int(seed), cp, cc), "ch_run_nudged")
     return cp, cc
 
 

@@ -454,14 +454,34 @@ static double round_storage(double v, int storage)
 
 static int ch_step_impl(i64 nx, i64 ny, double dx, double dy, double dt,
                         double D, double gamma, int nonlinear, int storage,
-                        const double *c_prev, const double *c_cur,
-                        double *c_next);
+                        unsigned long long nudge, const double *c_prev,
+                        const double *c_cur, double *c_next);
+
+/* Every nonzero coefficient w moved by one unit in the last place, up or
+ * down by the bits of a splitmix64 sequence started at seed (nudge = 0:
+ * unchanged).  A double evaluation of the scheme must round its window
+ * weights and band values; this gives another equally valid rounding, for
+ * measuring how far two such evaluations drift apart. */
+static unsigned long long splitmix64(unsigned long long *x)
+{
+    unsigned long long z = (*x += 0x9e3779b97f4a7c15ULL);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+static void nudge_ulp(double *w, int n, unsigned long long *state)
+{
+    for (int k = 0; k < n; ++k)
+        if (w[k] != 0.0)
+            w[k] = nextafter(w[k], (splitmix64(state) & 1) ? INFINITY : -INFINITY);
+}
 
 int orc_ch_step(i64 nx, i64 ny, double dx, double dy, double dt, double D,
                 double gamma, int nonlinear, const double *c_prev,
                 const double *c_cur, double *c_next)
 {
-    return ch_step_impl(nx, ny, dx, dy, dt, D, gamma, nonlinear, 0, c_prev,
+    return ch_step_impl(nx, ny, dx, dy, dt, D, gamma, nonlinear, 0, 0, c_prev,
                         c_cur, c_next);
 }
 
@@ -478,14 +498,14 @@ int orc_ch_step_stored(i64 nx, i64 ny, double dx, double dy, double dt,
 {
     if (storage < 0 || storage > 2)
         return -1;
-    return ch_step_impl(nx, ny, dx, dy, dt, D, gamma, nonlinear, storage,
+    return ch_step_impl(nx, ny, dx, dy, dt, D, gamma, nonlinear, storage, 0,
                         c_prev, c_cur, c_next);
 }
 
 static int ch_step_impl(i64 nx, i64 ny, double dx, double dy, double dt,
                         double D, double gamma, int nonlinear, int storage,
-                        const double *c_prev, const double *c_cur,
-                        double *c_next)
+                        unsigned long long nudge, const double *c_prev,
+                        const double *c_cur, double *c_next)
 {
     const i64 npts = nx * ny;
     if (nx < 5 || ny < 5)
@@ -507,6 +527,11 @@ static int ch_step_impl(i64 nx, i64 ny, double dx, double dy, double dt,
 
     biharmonic_5x5(dx, dy, wb);
     laplacian_5x5(dx, dy, wl);
+    unsigned long long nstate = nudge;
+    if (nudge) {
+        nudge_ulp(wb, 25, &nstate);
+        nudge_ulp(wl, 25, &nstate);
+    }
     if (orc_stencil2d(cbar, bih, nx, ny, nx, 2, 2, 2, 2, wb, 1, NULL, 0))
         goto done;
     if (nonlinear) {
@@ -528,8 +553,16 @@ static int ch_step_impl(i64 nx, i64 ny, double dx, double dy, double dt,
     {
         const double bx = a / (dx * dx * dx * dx);
         const double by = a / (dy * dy * dy * dy);
-        const double lx[5] = {bx, -4.0 * bx, 1.0 + 6.0 * bx, -4.0 * bx, bx};
-        const double ly[5] = {by, -4.0 * by, 1.0 + 6.0 * by, -4.0 * by, by};
+        double lx[5] = {bx, -4.0 * bx, 1.0 + 6.0 * bx, -4.0 * bx, bx};
+        double ly[5] = {by, -4.0 * by, 1.0 + 6.0 * by, -4.0 * by, by};
+        if (nudge) {
+            /* symmetric bands stay symmetric */
+            double hx[3] = {lx[2], lx[1], lx[0]}, hy[3] = {ly[2], ly[1], ly[0]};
+            nudge_ulp(hx, 3, &nstate);
+            nudge_ulp(hy, 3, &nstate);
+            lx[2] = hx[0]; lx[1] = lx[3] = hx[1]; lx[0] = lx[4] = hx[2];
+            ly[2] = hy[0]; ly[1] = ly[3] = hy[1]; ly[0] = ly[4] = hy[2];
+        }
         if (orc_cyclic_solve_grid(2, lx, 0, nx, ny, nx, rhs, w))
             goto done;
         if (storage)
@@ -565,6 +598,33 @@ int orc_ch_run_stored(i64 nx, i64 ny, double dx, double dy, double dt,
     for (i64 s = 0; s < nsteps; ++s) {
         if (orc_ch_step_stored(nx, ny, dx, dy, dt, D, gamma, nonlinear,
                                storage, c_prev, c_cur, nxt)) {
+            free(nxt);
+            return -1;
+        }
+        memcpy(c_prev, c_cur, sizeof(double) * npts);
+        memcpy(c_cur, nxt, sizeof(double) * npts);
+    }
+    free(nxt);
+    return 0;
+}
+
+/* nsteps steps of the double step with every window weight and band value
+ * moved by one ulp (nudge_ulp, seed != 0), the same coefficients at every
+ * step: another equally valid double rounding of the scheme's
+ * coefficients. */
+int orc_ch_run_nudged(i64 nx, i64 ny, double dx, double dy, double dt,
+                      double D, double gamma, int nonlinear, i64 nsteps,
+                      unsigned long long seed, double *c_prev, double *c_cur)
+{
+    const i64 npts = nx * ny;
+    if (!seed)
+        return -1;
+    double *nxt = (double *)malloc(sizeof(double) * npts);
+    if (!nxt)
+        return -1;
+    for (i64 s = 0; s < nsteps; ++s) {
+        if (ch_step_impl(nx, ny, dx, dy, dt, D, gamma, nonlinear, 0, seed,
+                         c_prev, c_cur, nxt)) {
             free(nxt);
             return -1;
         }

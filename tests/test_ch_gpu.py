@@ -175,8 +175,8 @@ def test_ch_4096_one_step_parity():
 
 
 # Allowed multiple of the oracle's own rounding spread for the long FP64
-# runs (see the test below).
-SPREAD_MULTIPLE = 64
+# runs (see the test below); the GPU has measured 0.4 to 0.7 of it.
+SPREAD_MULTIPLE = 2
 
 
 @pytest.mark.parametrize("case", [0, 1], ids=["1024x1000", "4096x20"])
@@ -186,9 +186,13 @@ def test_ch_long_horizon_parity_at_sampled_points(case):
     by make_ch_long.py from the oracle alone) on a full row, a full column
     and 2048 seeded points.  The bound is a fixed multiple of the oracle's
     own rounding spread at that checkpoint: the largest difference between
-    the oracle's run and its run from the transposed initial field
-    (transposed back), two equally valid double evaluations of the same
-    scheme on a square grid.  The GPU's mass equals the oracle's plain sum
+    the oracle's run and three equally valid double evaluations of the same
+    scheme on a square grid, the runs from the transposed and from the
+    doubly reflected initial field (mapped back), and the run whose window
+    weights and band values are rounded the other way in their last place.
+    The last grows linearly with the steps, as the GPU's difference does: a
+    second evaluation rounds the coefficients its own way and repeats that
+    difference at every step.  The GPU's mass equals the oracle's plain sum
     to 1e-12 of sum |C^0|."""
     ref = golden("ch_long_parity.json")["cases"][case]
     n = ref["n"]

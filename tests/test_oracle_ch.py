@@ -190,3 +190,23 @@ def test_stored_run_continues_the_stored_step():
         cp, cc = cc, oracle.ch_step_stored(cp, cc, dx, dy, dt, "bf16")
     rp, rc = oracle.ch_run_stored(c0, c0, 5, dx, dy, dt, "bf16")
     assert np.array_equal(rc, cc) and np.array_equal(rp, cp)
+
+
+def test_nudged_run_is_a_one_ulp_perturbation():
+    """ch_run_nudged moves every coefficient of the step by one ulp: its run
+    differs from ch_run, by no more than a few roundings of the step's terms
+    per step, is fixed by its seed, and differs between seeds."""
+    ny, nx = 32, 48
+    dx, dy = 2 * math.pi / nx, 2 * math.pi / ny
+    dt = 0.1 * dx * dx
+    c0 = 0.1 * np.random.default_rng(4).uniform(-1, 1, (ny, nx))
+    _, ref = oracle.ch_run(c0, c0, 6, dx, dy, dt)
+    _, a = oracle.ch_run_nudged(c0, c0, 6, dx, dy, dt, seed=1)
+    _, a2 = oracle.ch_run_nudged(c0, c0, 6, dx, dy, dt, seed=1)
+    _, b = oracle.ch_run_nudged(c0, c0, 6, dx, dy, dt, seed=2)
+    assert np.array_equal(a, a2)
+    assert not np.array_equal(a, b)
+    d = np.abs(a - ref).max()
+    assert 0 < d <= 6 * 64 * 2.0 ** -52 * np.abs(c0).max(), d
+    with pytest.raises(ValueError):
+        oracle.ch_run_nudged(c0, c0, 1, dx, dy, dt, seed=0)
