@@ -315,12 +315,15 @@ def bench_ch(torch, b, wl, n, steps, warmup):
     sec, _ = time_loop(torch, lambda: b.mxs_ch_step(p, 1, True), steps, warmup)
     m = b.mxs_ch_mass(p)[0]
     forms = {}
-    if n <= 1024:      # rows of at most 1024 elements: both step forms
-        for mode, key in ((b.MXS_CH_PERSISTENT, "persistent"), (b.MXS_CH_SEPARATE, "separate")):
-            b.mxs_ch_set_step_mode(p, mode)
-            fs, _ = time_loop(torch, lambda: b.mxs_ch_step(p, 1, True), steps, warmup)
-            forms[f"{key}_steps_per_s"] = steps / fs
-        b.mxs_ch_mass(p)
+    # every step form the grid allows, each graph-replayed (the persistent
+    # one for rows of at most 1024 elements)
+    modes = (((b.MXS_CH_PERSISTENT, "persistent"),) if n <= 1024 else ()) + \
+        ((b.MXS_CH_FUSED, "fused"), (b.MXS_CH_SEPARATE, "separate"))
+    for mode, key in modes:
+        b.mxs_ch_set_step_mode(p, mode)
+        fs, _ = time_loop(torch, lambda: b.mxs_ch_step(p, 1, True), steps, warmup)
+        forms[f"{key}_steps_per_s"] = steps / fs
+    b.mxs_ch_mass(p)
     b.mxs_destroy(p)
     per = sec / steps
     floor = 56 * n * n
@@ -350,9 +353,11 @@ def bench_ensemble(torch, b, wl, steps, warmup):
         out[f"ensemble_{name}_layout"] = b.mxs_plan_info(p)
         sec, _ = time_loop(torch, lambda: b.mxs_ch_step(p, 1, True), steps, warmup)
         out[f"ensemble_{name}_steps_per_s"] = steps / sec
-        # both step forms, each graph-replayed: one persistent launch per
-        # step, and the separate launches
-        for mode, key in ((b.MXS_CH_PERSISTENT, "persistent"), (b.MXS_CH_SEPARATE, "separate")):
+        # every step form, each graph-replayed: one persistent launch per
+        # step, the right-hand side inside the row solves, and the separate
+        # launches
+        for mode, key in ((b.MXS_CH_PERSISTENT, "persistent"), (b.MXS_CH_FUSED, "fused"),
+                          (b.MXS_CH_SEPARATE, "separate")):
             b.mxs_ch_set_step_mode(p, mode)
             sec, _ = time_loop(torch, lambda: b.mxs_ch_step(p, 1, True), steps, warmup)
             out[f"ensemble_{name}_{key}_steps_per_s"] = steps / sec

@@ -270,10 +270,15 @@ mxs_status mxs_ch_step(mxs_plan plan, int nsteps, int use_graph, void *hip_strea
  * and meet at a grid barrier between the phases (rows of at most 1024
  * elements; else MXS_ERR_UNSUPPORTED, as when the device cannot hold the
  * grid).  The barrier's wait is bounded: a barrier that times out makes the
- * launch end early, and the next mxs_ch_mass returns MXS_ERR_HIP.  Plans
- * start in MXS_CH_SEPARATE; mxs_autotune times both and keeps the faster.
- * With use_graph the persistent launch is captured in the step's graph. */
-enum { MXS_CH_SEPARATE = 0, MXS_CH_PERSISTENT = 1 };
+ * launch end early, and the next mxs_ch_mass returns MXS_ERR_HIP.
+ * MXS_CH_FUSED: the right-hand side of the x sweep is formed inside the row
+ * solves, so that it never goes to memory (one launch per register class of
+ * rows, then the three column phases; rows of at most 4096 elements, else
+ * MXS_ERR_UNSUPPORTED).  The three give the same step up to the order of
+ * rounding.  Plans start in MXS_CH_SEPARATE; mxs_autotune times every mode
+ * the plan supports and keeps the fastest.  With use_graph the persistent
+ * launch is captured in the step's graph. */
+enum { MXS_CH_SEPARATE = 0, MXS_CH_PERSISTENT = 1, MXS_CH_FUSED = 2 };
 mxs_status mxs_ch_set_step_mode(mxs_plan plan, int mode);
 
 /* Device pointers of C^{n-1} and C^n of instance k (k = 0 for one grid). */

@@ -40,7 +40,7 @@ MXS_X, MXS_Y, MXS_XY = 0, 1, 2
 MXS_NP, MXS_P = 0, 1
 MXS_F64, MXS_F32, MXS_BF16 = 0, 1, 2
 MXS_LINES_RAGGED, MXS_LINES_ROWS, MXS_LINES_COLS = 0, 1, 2
-MXS_CH_SEPARATE, MXS_CH_PERSISTENT = 0, 1
+MXS_CH_SEPARATE, MXS_CH_PERSISTENT, MXS_CH_FUSED = 0, 1, 2
 
 
 class MxsError(RuntimeError):
@@ -309,7 +309,8 @@ def mxs_ch_coarsening(plan, k=0, stream=None):
 
 
 def mxs_ch_set_step_mode(plan, mode):
-    """MXS_CH_SEPARATE or MXS_CH_PERSISTENT (one launch per step)."""
+    """MXS_CH_SEPARATE, MXS_CH_PERSISTENT (one launch per step) or MXS_CH_FUSED
+    (the right-hand side formed inside the row solves)."""
     _check(_lib.mxs_ch_set_step_mode(plan, mode))
 
 

@@ -6,6 +6,9 @@
 //   2. L_x w = R on every row, in place                        (cyclic.hip)
 //   3-5. L_y v = w on every column, three phases, the last one
 //        writing C^{n+1} = 2 C^n - C^{n-1} + v                  (cyclic.hip)
+// In the fused mode steps 1 and 2 are one launch per register class of the
+// rows (chrows.hip): each workgroup forms R of a few rows in registers and
+// solves them, and R never goes to memory.
 // The three state buffers rotate, so the kernel arguments differ between
 // consecutive steps; the plan keeps one instance table (and one captured
 // HIP graph) per rotation.
@@ -98,6 +101,30 @@ struct CHPlan final : mxs_plan_s {
     // row fits register class kPersistNBMax; bar holds the grid barrier's
     // words (arrivals, generation, exits, error)
     bool persistent = false, persist_ok = false;
+    // right-hand side formed inside the row solves (one launch per register
+    // class of rows over groups of fused_rows rows, 4 or 8): eligible when
+    // every row fits a register class; fused_work lists the row groups,
+    // class by class
+    bool fused = false, fused_ok = false;
+    int fused_rows = 4;
+    DevBuf fused_work;
+    std::vector<RowRange> fused_ranges;
+    std::vector<int> class_order;   // instances ordered by register class of their rows
+
+    // Row groups of wr rows for the fused form, in class order.
+    hipError_t build_fused(int wr) {
+        std::vector<RowGroup> work;
+        fused_ranges.clear();
+        for (int g : class_order) {
+            const int nb = wave_nb(inst[g].nx);
+            if (fused_ranges.empty() || fused_ranges.back().nb != nb)
+                fused_ranges.push_back({nb, static_cast<int>(work.size()), 0});
+            for (int j0 = 0; j0 < inst[g].ny; j0 += wr) work.push_back({g, j0});
+            fused_ranges.back().count = static_cast<int>(work.size()) - fused_ranges.back().first;
+        }
+        fused_rows = wr;
+        return fused_work.upload(work.data(), sizeof(RowGroup) * work.size());
+    }
     int persist_grid = 0, persist_nbmax = 1, spin_limit = 1 << 22;
     DevBuf bar;
 
@@ -117,6 +144,7 @@ struct CHPlan final : mxs_plan_s {
         drop_graphs();
         persist_nograph = false;
         persistent = on;
+        if (on) fused = false;
         if (on) rhs_threads = kPersistThreads;
         return build_rhs(rows);
     }
@@ -155,10 +183,21 @@ struct CHPlan final : mxs_plan_s {
             pa.stage_bytes = static_cast<int>(persist_stage_bytes(dtype, persist_nbmax));
             return launch_ch_persistent(dtype, persist_nbmax, pa, persist_grid, s);
         }
+        const RowsInst *ri = static_cast<const RowsInst *>(rows_d.ptr);
+        if (fused) {
+            hipError_t e = hipSuccess;
+            const RowGroup *work = static_cast<const RowGroup *>(fused_work.ptr);
+            for (size_t q = 0; q < fused_ranges.size() && e == hipSuccess; ++q)
+                e = launch_ch_rhs_rows(dtype, fused_rows, fused_ranges[q].nb,
+                                       static_cast<const RhsInst *>(rhs_d[r].ptr), ri, work + fused_ranges[q].first,
+                                       fused_ranges[q].count, s);
+            if (e != hipSuccess) return e;
+            return launch_cols(wdtype, dtype, 2, 1, static_cast<const ColsInst *>(cols_d[r].ptr),
+                               map_of(colsAC_map), map_of(colsB_map), colsAC, colsB, bgroups, s);
+        }
         hipError_t e = launch_ch_rhs(dtype, static_cast<const RhsInst *>(rhs_d[r].ptr),
                                      map_of(rhs_map), rhs_blocks, rhs_threads, s);
         if (e != hipSuccess) return e;
-        const RowsInst *ri = static_cast<const RowsInst *>(rows_d.ptr);
         if (row_ranges.empty())
             e = launch_rows(wdtype, 2, ri, map_of(rows_map), row_lines, row_nw, row_grid, row_lds, s);
         for (size_t q = 0; q < row_ranges.size() && e == hipSuccess; ++q)
@@ -383,6 +422,8 @@ struct CHPlan final : mxs_plan_s {
             int threads, rows, w;
             bool pers;
             double t;
+            bool fus = false;
+            int fr = 4;   // rows per workgroup of the fused form
         };
         std::vector<Cand> cands;
         for (int threads : {256, 128, 64})
@@ -395,17 +436,28 @@ struct CHPlan final : mxs_plan_s {
         // the persistent step (one launch), right-hand side chunks of each height
         if (persist_ok)
             for (int rows : {4, 8, 16, 32}) cands.push_back({kPersistThreads, rows, row_nw, true, 1e30});
+        // the right-hand side inside the row solves (no right-hand side tiles to shape)
+        if (fused_ok)
+            for (int fr : {4, 8})
+                if (ch_rhs_rows_lds_bytes(dtype, fr, wave_nb(max_nx)) <= static_cast<size_t>(device_lds_limit()))
+                    cands.push_back({kRhsThreads, 16, row_nw, false, 1e30, true, fr});
         if (cands.empty()) return MXS_OK;
         for (int pass = 0; pass < 2; ++pass)
             for (Cand &c : cands) {
                 persistent = c.pers;
+                fused = c.fus;
                 rhs_threads = c.threads;
                 mxs_status st = build_rhs(c.rows);
                 if (st) return st;
+                if (c.fus && c.fr != fused_rows) {
+                    hipError_t fe = build_fused(c.fr);
+                    if (fe != hipSuccess) return hip_fail(fe, "row group table upload");
+                }
                 set_row_waves(c.w);
                 const double t = time_launches([&] { return enqueue(r, s); }, s, 2, 10);
                 if (t < 0) {
                     persistent = false;
+                    fused = false;
                     return hip_fail(hipGetLastError(), "autotune launch");
                 }
                 c.t = std::min(c.t, t);
@@ -419,29 +471,49 @@ struct CHPlan final : mxs_plan_s {
                 best_persist_t = c.t;
             }
         for (const Cand &c : cands)
-            if (!c.pers && c.t < best_graph_t) best_graph_t = c.t;
+            if (!c.pers && !c.fus && c.t < best_graph_t) {
+                best_graph_t = c.t;
+                sep_threads = c.threads;
+                sep_rows = c.rows;
+            }
+        for (const Cand &c : cands)
+            if (c.fus && c.t < best_fused_t) best_fused_t = c.t;
         set_row_waves(best->w);
         persistent = best->pers;
+        fused = best->fus;
         persist_nograph = false;
+        if (fused_ok && best->fr != fused_rows) {
+            hipError_t fe = build_fused(best->fus ? best->fr : 4);
+            if (fe != hipSuccess) return hip_fail(fe, "row group table upload");
+        }
         rhs_threads = best->threads;
         return build_rhs(best->rows);
     }
 
     // step times of the best candidate of each mode at the last autotune
     bool best_persist = false;
-    double best_persist_t = 0, best_graph_t = 1e30;
+    double best_persist_t = 0, best_graph_t = 1e30, best_fused_t = 1e30;
+    // right-hand side layout of the fastest separate-launch candidate (0: not tuned)
+    int sep_threads = kRhsThreads, sep_rows = 0;
 
     void info(char *buf, int len) const override {
-        const int launches = persistent ? 1 : 1 + (row_ranges.empty() ? 1 : static_cast<int>(row_ranges.size())) + 3;
+        const int launches = persistent ? 1
+                             : fused  ? static_cast<int>(fused_ranges.size()) + 3
+                                      : 1 + (row_ranges.empty() ? 1 : static_cast<int>(row_ranges.size())) + 3;
         int n = snprintf(buf, len, "ch instances=%d dtype=%d step=%s launches_per_step=%d rhs_rows=%d rhs_threads=%d "
                          "rhs_blocks=%d cols_blocks=%d colsB_groups=%d",
-                         ninst(), dtype, persistent ? "persistent" : "separate", launches, rhs_rows, rhs_threads,
+                         ninst(), dtype, persistent ? "persistent" : fused ? "fused" : "separate", launches, rhs_rows,
+                         rhs_threads,
                          rhs_blocks, colsAC, bgroups);
         if (persistent && n < len)
             n += snprintf(buf + n, len - n, " persist_grid=%d persist_graph=%d", persist_grid, persist_nograph ? 0 : 1);
+        if (best_graph_t < 1e29 && n < len)
+            n += snprintf(buf + n, len - n, " tuned_us_separate=%.1f", best_graph_t * 1e6);
         if (best_persist && n < len)
-            n += snprintf(buf + n, len - n, " tuned_us_separate=%.1f tuned_us_persistent=%.1f", best_graph_t * 1e6,
-                          best_persist_t * 1e6);
+            n += snprintf(buf + n, len - n, " tuned_us_persistent=%.1f", best_persist_t * 1e6);
+        if (fused && n < len) n += snprintf(buf + n, len - n, " fused_rows=%d", fused_rows);
+        if (best_fused_t < 1e29 && n < len)
+            n += snprintf(buf + n, len - n, " tuned_us_fused=%.1f", best_fused_t * 1e6);
         if (row_ranges.empty() && n < len)
             n += snprintf(buf + n, len - n, " row_kernel=lds row_waves=%d row_grid=%d", row_nw, row_grid);
         for (size_t q = 0; q < row_ranges.size() && n < len; ++q)
@@ -536,6 +608,16 @@ struct CHPlan final : mxs_plan_s {
             line += inst[g].ny;
         }
         row_lines = line;
+        fused_ranges.clear();
+        fused_ok = false;
+        class_order = by_class;
+        if (reg_rows) {
+            // rows per fused workgroup: 4 until tuned; MXS_CH_FUSED_ROWS=8 picks 8 (tests)
+            const char *fr = getenv("MXS_CH_FUSED_ROWS");
+            hipError_t fe = build_fused(fr && atoi(fr) == 8 ? 8 : 4);
+            if (fe != hipSuccess) return hip_fail(fe, "row group table upload");
+            fused_ok = true;
+        }
         colsAC = bAC;
         colsB = bB;
         max_nx = maxnx;
@@ -607,11 +689,13 @@ struct CHPlan final : mxs_plan_s {
             }
         }
         if (const char *env = getenv("MXS_PERSIST_SPIN")) spin_limit = std::max(0, atoi(env));
-        if (const char *env = getenv("MXS_CH_STEP"))
+        if (const char *env = getenv("MXS_CH_STEP")) {
             if (env[0] == 'p' && persist_ok) {
                 mxs_status st = set_persistent(true, 0);
                 if (st) return st;
             }
+            if (env[0] == 'f' && fused_ok) fused = true;
+        }
         return MXS_OK;
     }
 };
@@ -713,10 +797,24 @@ mxs_status mxs_ch_step(mxs_plan plan, int nsteps, int use_graph, void *hip_strea
 mxs_status mxs_ch_set_step_mode(mxs_plan plan, int mode) {
     CHPlan *p = as_ch(plan);
     if (!p) return fail(MXS_ERR_BAD_HANDLE, "not a Cahn-Hilliard plan");
-    if (mode != MXS_CH_SEPARATE && mode != MXS_CH_PERSISTENT)
-        return fail(MXS_ERR_INVALID_ARG, "mode must be MXS_CH_SEPARATE or MXS_CH_PERSISTENT");
-    if (mode == MXS_CH_SEPARATE && p->persistent) p->rhs_threads = kRhsThreads;
-    return p->set_persistent(mode == MXS_CH_PERSISTENT, p->rhs_rows);
+    if (mode != MXS_CH_SEPARATE && mode != MXS_CH_PERSISTENT && mode != MXS_CH_FUSED)
+        return fail(MXS_ERR_INVALID_ARG, "mode must be MXS_CH_SEPARATE, MXS_CH_PERSISTENT or MXS_CH_FUSED");
+    if (mode == MXS_CH_FUSED && !p->fused_ok)
+        return fail(MXS_ERR_UNSUPPORTED, "this plan cannot form the right-hand side inside the row solves");
+    int rows = p->rhs_rows;
+    if (mode != MXS_CH_PERSISTENT) {
+        // the separate launches take the right-hand side layout tuned for them
+        if (p->sep_rows > 0) {
+            p->rhs_threads = p->sep_threads;
+            rows = p->sep_rows;
+        } else if (p->persistent) {
+            p->rhs_threads = kRhsThreads;
+            rows = 0;
+        }
+    }
+    mxs_status st = p->set_persistent(mode == MXS_CH_PERSISTENT, rows);
+    if (st == MXS_OK) p->fused = mode == MXS_CH_FUSED;
+    return st;
 }
 
 mxs_status mxs_ch_state(mxs_plan plan, int k, void **c_prev, void **c_cur) {

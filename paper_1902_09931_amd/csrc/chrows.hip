@@ -1,0 +1,237 @@
+// The x sweep of the ADI Cahn-Hilliard step (Sec. 5.1) with its right-hand
+// side formed inside the row solves, so that R never goes to memory:
+//
+//   L_x w = R,  R = cdiff (C^n - C^{n-1}) + sum wb * Cbar + sum wl * (C^n^3 - C^n),
+//
+// Cbar = 2 C^n - C^{n-1} (the terms as in ch.h).  A workgroup of WR
+// wavefronts (WR = 4 or 8) takes WR consecutive rows of one instance.  The
+// rows are walked in sub-blocks of 64 WR columns: for each, every thread
+// requests one column of the WR + 4 input rows of C^n and C^{n-1} the rows'
+// windows reach (periodic in both directions; two halo columns on each side
+// from 4 (WR + 4) threads), the workgroup stages Cbar, C^n^3 - C^n and
+// C^n - C^{n-1} in LDS, and each wavefront forms R of its own row at the
+// sub-block's columns, directly in the register layout the line solver
+// starts from (element BLK c + 64 k + lane of the line in raw[c][k] of lane
+// `lane`).  With four rows the next sub-block's values are requested before
+// the current one is staged.  Then every wavefront solves its row in
+// registers (the register line solver of wave_dev.h) and stores w.
+//
+// Memory: C^n and C^{n-1} are read once per workgroup, WR + 4 rows for WR
+// rows of output; the 4 rows a workgroup shares with its neighbours come from
+// L2 when the neighbours run at the same time (row groups in one contiguous
+// band per XCD).  Only w is written: 2 words read and 1 written per point,
+// against 3 + 2 for the right-hand side and row solve as two kernels.
+#include "ch_dev.h"
+#include "wave_dev.h"
+
+namespace mxs {
+
+namespace {
+
+// Geometry of a workgroup of WR rows: 64 WR threads, sub-blocks of 64 WR
+// columns (one per thread), WR + 4 input rows per sub-block, LDS rows with
+// two halo columns on each side.
+template <int WR> struct FusedShape {
+    static constexpr int SUB = 64 * WR;
+    static constexpr int GIN = WR + 4;
+    static constexpr int LW = SUB + 4;
+};
+
+template <typename T, typename TW, int NB, int WR>
+__global__ void __launch_bounds__(64 * WR) ch_rhs_rows_kernel(const RhsInst *__restrict__ rhs,
+                                                              const RowsInst *__restrict__ rows,
+                                                              const RowGroup *__restrict__ work, int count) {
+    using A = typename St<T>::acc;
+    using FS = FusedShape<WR>;
+    constexpr int SUB = FS::SUB, GIN = FS::GIN, LW = FS::LW;
+    constexpr int E = WaveShape<NB>::E, NBB = WaveShape<NB>::NBB;
+    constexpr int BLK = 64 * E;
+    constexpr int NST = (NBB * BLK + SUB - 1) / SUB;   // sub-blocks of the longest line of the class
+    constexpr int MPS = SUB / 64;                       // columns per lane and sub-block
+    // Eight rows per workgroup hold twice the values per thread in flight;
+    // their next sub-block is not requested early (the registers would not
+    // fit beside the line), four rows' is.
+    constexpr bool PREFETCH = WR <= 4;
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    A *lb = reinterpret_cast<A *>(smem_raw);   // Cbar           [GIN][LW]
+    A *lf = lb + GIN * LW;                     // C^3 - C        [GIN][LW]
+    A *ld = lf + GIN * LW;                     // C^n - C^{n-1}  [WR][SUB]
+
+    const RowGroup g = work[xcd_tile(blockIdx.x, count)];
+    const RhsInst &I = rhs[g.inst];
+    const RowsInst &RI = rows[g.inst];
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int nx = I.nx, ny = I.ny, j0 = g.j0;
+    const int nsub = ((nx - 1) / BLK + 1) * BLK;   // columns of the line's blocks
+    const gptr<const T> cur = as_global(static_cast<const T *>(I.cur));
+    const gptr<const T> prev = as_global(static_cast<const T *>(I.prev));
+
+    A wb[25], wl[9];
+#pragma unroll
+    for (int k = 0; k < 25; ++k) wb[k] = bih_tap(k / 5, k % 5) ? wb_of<A>(I, k) : A(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) wl[k] = lap_tap(k / 3, k % 3) ? wl_of<A>(I, k) : A(0);
+    const A cdiff = cd_of<A>(I);
+
+    long long roff[GIN];   // offsets of the input rows j0 - 2 .. j0 + WR + 1
+#pragma unroll
+    for (int u = 0; u < GIN; ++u) roff[u] = wrap_fast(static_cast<long long>(j0) - 2 + u, ny) * nx;
+    // halo: thread t < 4 GIN loads halo slot h = t % 4 of input row t / 4
+    const int hu = min(t >> 2, GIN - 1), hh = t & 3;
+
+    // request the values of sub-block st (columns SUB st ..)
+    auto load = [&](int st, A (&c)[GIN], A (&p)[GIN], A &hc, A &hp) __attribute__((always_inline)) {
+        const long long cb = static_cast<long long>(st) * SUB;
+        const long long col = wrap_fast(cb + t, nx);
+#pragma unroll
+        for (int u = 0; u < GIN; ++u) {
+            c[u] = to_acc<T>(gld<T>(cur, roff[u] + col));
+            p[u] = to_acc<T>(gld<T>(prev, roff[u] + col));
+        }
+        hc = A(0);
+        hp = A(0);
+        if (t < 4 * GIN) {
+            const long long hcol = wrap_fast(hh < 2 ? cb - 2 + hh : cb + SUB + (hh - 2), nx);
+            hc = to_acc<T>(gld<T>(cur, roff[hu] + hcol));
+            hp = to_acc<T>(gld<T>(prev, roff[hu] + hcol));
+        }
+    };
+
+    TW raw[NBB][E];
+#pragma unroll
+    for (int c = 0; c < NBB; ++c)
+#pragma unroll
+        for (int k = 0; k < E; ++k) raw[c][k] = TW(0);
+
+    A c0[GIN], p0[GIN], c1[GIN], p1[GIN], hc0, hp0, hc1, hp1;
+    load(0, c0, p0, hc0, hp0);
+#pragma unroll
+    for (int st = 0; st < NST; ++st) {
+        if (st * SUB >= nsub) continue;   // uniform: past the line's last block
+        if (!PREFETCH && st > 0) load(st, c0, p0, hc0, hp0);
+        __syncthreads();                  // the previous sub-block's LDS reads are done
+#pragma unroll
+        for (int u = 0; u < GIN; ++u) {
+            const A cv = c0[u], pv = p0[u];
+            lb[u * LW + 2 + t] = A(2) * cv - pv;
+            if (u >= 1 && u <= GIN - 2) lf[u * LW + 2 + t] = cv * cv * cv - cv;
+            if (u >= 2 && u < 2 + WR) ld[(u - 2) * SUB + t] = cv - pv;
+        }
+        if (t < 4 * GIN) {
+            const int slot = hu * LW + (hh < 2 ? hh : SUB + hh);
+            lb[slot] = A(2) * hc0 - hp0;
+            lf[slot] = hc0 * hc0 * hc0 - hc0;
+        }
+        // the next sub-block's requests overlap this one's arithmetic
+        if (PREFETCH && st + 1 < NST && (st + 1) * SUB < nsub) load(st + 1, c1, p1, hc1, hp1);
+        __syncthreads();
+
+#pragma unroll
+        for (int m = 0; m < MPS; ++m) {
+            // column SUB st + 64 m + lane of the line: element BLK c + 64 k + lane
+            const int x0 = st * SUB + 64 * m;   // compile time after unrolling
+            const int c = x0 / BLK, k = (x0 % BLK) / 64;
+            if (c >= NBB) continue;
+            const int o = 64 * m + lane;   // column within the sub-block
+            A acc = A(0);
+#pragma unroll
+            for (int q = 0; q < 5; ++q)
+#pragma unroll
+                for (int pp = 0; pp < 5; ++pp)
+                    if (bih_tap(q, pp)) acc = fma(wb[q * 5 + pp], lb[(w + q) * LW + o + pp], acc);
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int pp = 0; pp < 3; ++pp)
+                    if (lap_tap(q, pp)) acc = fma(wl[q * 3 + pp], lf[(w + 1 + q) * LW + o + 1 + pp], acc);
+            acc = fma(cdiff, ld[w * SUB + o], acc);
+            raw[c][k] = static_cast<TW>(acc);
+        }
+        if constexpr (PREFETCH) {
+#pragma unroll
+            for (int u = 0; u < GIN; ++u) {
+                c0[u] = c1[u];
+                p0[u] = p1[u];
+            }
+            hc0 = hc1;
+            hp0 = hp1;
+        }
+    }
+    __syncthreads();   // the LDS becomes the wavefronts' solver stages
+
+    if (j0 + w >= ny) return;
+    LineRef L;
+    L.in = nullptr;
+    L.out = static_cast<TW *>(RI.out) + static_cast<long long>(j0 + w) * RI.ld;
+    L.n = nx;
+    L.p1 = RI.p1;
+    L.p2 = RI.p2;
+    L.invK = RI.invK;
+    L.pow = RI.pow;
+    TW *stage = reinterpret_cast<TW *>(smem_raw) + static_cast<size_t>(w) * Stage<TW, E>::SIZE;
+    wave_solve<TW, 2, NB>(L, raw, stage);
+}
+
+template <typename T, typename TW, int WR>
+size_t lds_bytes_of(int nb) {
+    using A = typename St<T>::acc;
+    using FS = FusedShape<WR>;
+    const int E = nb <= 1 ? WaveShape<1>::E : nb <= 2 ? WaveShape<2>::E : WaveShape<4>::E;
+    const size_t rhs = (static_cast<size_t>(2) * FS::GIN * FS::LW + static_cast<size_t>(WR) * FS::SUB) * sizeof(A);
+    const size_t stage = static_cast<size_t>(WR) * 64 * (E + 16 / sizeof(TW)) * sizeof(TW);
+    return rhs > stage ? rhs : stage;
+}
+
+template <typename T, typename TW, int NB, int WR>
+hipError_t launch_nb(const RhsInst *rhs, const RowsInst *rows, const RowGroup *work, int count, hipStream_t s) {
+    const size_t lds = lds_bytes_of<T, TW, WR>(NB);
+    hipLaunchKernelGGL((ch_rhs_rows_kernel<T, TW, NB, WR>), dim3(count), dim3(64 * WR), lds, s, rhs, rows,
+                       work, count);
+    return hipGetLastError();
+}
+
+template <typename T, typename TW, int WR>
+hipError_t launch_t(int nb, const RhsInst *rhs, const RowsInst *rows, const RowGroup *work, int count,
+                    hipStream_t s) {
+    switch (nb) {
+    case 1: return launch_nb<T, TW, 1, WR>(rhs, rows, work, count, s);
+    case 2: return launch_nb<T, TW, 2, WR>(rhs, rows, work, count, s);
+    case 4: return launch_nb<T, TW, 4, WR>(rhs, rows, work, count, s);
+    case 8: return launch_nb<T, TW, 8, WR>(rhs, rows, work, count, s);
+    case 16: return launch_nb<T, TW, 16, WR>(rhs, rows, work, count, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, typename TW>
+hipError_t launch_wr(int wr, int nb, const RhsInst *rhs, const RowsInst *rows, const RowGroup *work, int count,
+                     hipStream_t s) {
+    if (wr == 4) return launch_t<T, TW, 4>(nb, rhs, rows, work, count, s);
+    if (wr == 8) return launch_t<T, TW, 8>(nb, rhs, rows, work, count, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+size_t ch_rhs_rows_lds_bytes(int state_dtype, int wr, int nb) {
+    if (wr != 4 && wr != 8) return 0;
+    switch (state_dtype) {
+    case F64: return wr == 4 ? lds_bytes_of<double, double, 4>(nb) : lds_bytes_of<double, double, 8>(nb);
+    case F32: return wr == 4 ? lds_bytes_of<float, float, 4>(nb) : lds_bytes_of<float, float, 8>(nb);
+    default: return wr == 4 ? lds_bytes_of<bf16, float, 4>(nb) : lds_bytes_of<bf16, float, 8>(nb);
+    }
+}
+
+hipError_t launch_ch_rhs_rows(int state_dtype, int wr, int nb, const RhsInst *rhs, const RowsInst *rows,
+                              const RowGroup *work, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    switch (state_dtype) {
+    case F64: return launch_wr<double, double>(wr, nb, rhs, rows, work, count, s);
+    case F32: return launch_wr<float, float>(wr, nb, rhs, rows, work, count, s);
+    case BF16: return launch_wr<bf16, float>(wr, nb, rhs, rows, work, count, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mxs

@@ -320,13 +320,17 @@ __device__ __forceinline__ void wave_solve(const LineRef &L,
 #pragma unroll
                 for (int j = 0; j < E; ++j) buf[lane * CH + j] = from_f64<T>(v[c][j]);
                 wave_sync();
+                // every value of the block out of LDS first, then the stores:
+                // one wait for the LDS reads instead of one per store
+                T ov[E];
+#pragma unroll
+                for (int k = 0; k < E; ++k) ov[k] = buf[LPC * k * CH + wslot];
+                wave_sync();
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
                     const int idx = BLK * c + 64 * k + lane;
-                    const T val = buf[LPC * k * CH + wslot];
-                    if (c < last || idx < n) gst<T>(out, static_cast<unsigned>(idx), val);
+                    if (c < last || idx < n) gst<T>(out, static_cast<unsigned>(idx), ov[k]);
                 }
-                wave_sync();
             }
         }
     }

@@ -179,8 +179,9 @@ def test_ch_4096_one_step_parity():
 SPREAD_MULTIPLE = 2
 
 
+@pytest.mark.parametrize("mode", ["separate", "fused"])
 @pytest.mark.parametrize("case", [0, 1], ids=["1024x1000", "4096x20"])
-def test_ch_long_horizon_parity_at_sampled_points(case):
+def test_ch_long_horizon_parity_at_sampled_points(case, mode):
     """FP64 over many steps: 1024^2 to 1000 steps and 4096^2 to 20 steps,
     compared at every checkpoint of tests/golden/ch_long_parity.json (written
     by make_ch_long.py from the oracle alone) on a full row, a full column
@@ -193,13 +194,15 @@ def test_ch_long_horizon_parity_at_sampled_points(case):
     The last grows linearly with the steps, as the GPU's difference does: a
     second evaluation rounds the coefficients its own way and repeats that
     difference at every step.  The GPU's mass equals the oracle's plain sum
-    to 1e-12 of sum |C^0|."""
+    to 1e-12 of sum |C^0|.  Both step forms: the separate launches and the
+    right-hand side formed inside the row solves."""
     ref = golden("ch_long_parity.json")["cases"][case]
     n = ref["n"]
     c0 = wl.ch_initial(n, n, seed=2)
     g = Grid(c0)
     rows = []
     try:
+        b.mxs_ch_set_step_mode(g.plan, b.MXS_CH_FUSED if mode == "fused" else b.MXS_CH_SEPARATE)
         assert g.dt == pytest.approx(ref["dt"], rel=1e-15)
         done = 0
         for cp in ref["checkpoints"]:
@@ -215,7 +218,7 @@ def test_ch_long_horizon_parity_at_sampled_points(case):
     finally:
         g.close()
     for k, diff, spread, dm in rows:
-        print(f"n={n} step {k}: |GPU - oracle| {diff:.3e}, oracle spread {spread:.3e}, "
+        print(f"{mode} n={n} step {k}: |GPU - oracle| {diff:.3e}, oracle spread {spread:.3e}, "
               f"ratio {diff / spread:.2f}, mass difference {dm:.2e}")
     for k, diff, spread, dm in rows:
         assert diff <= SPREAD_MULTIPLE * spread, k
@@ -250,9 +253,10 @@ def rhs_term_bound(cp, cc, dx, dy, dt):
 LINV = 1.15
 
 
+@pytest.mark.parametrize("mode", ["separate", "fused"])
 @pytest.mark.parametrize("dt_name,shape", [("f32", (128, 128)), ("bf16", (128, 128)),
                                            ("f32", (96, 160)), ("bf16", (96, 160))])
-def test_ch_reduced_precision_one_step_derived_bound(dt_name, shape):
+def test_ch_reduced_precision_one_step_derived_bound(dt_name, shape, mode):
     """From the same stored state, one GPU step against one step of the
     stored-precision oracle (double arithmetic, R and w rounded to float,
     C^{n+1} to the storage dtype).  The two differ only by the float
@@ -269,6 +273,7 @@ def test_ch_reduced_precision_one_step_derived_bound(dt_name, shape):
         b.mxs_ch_step(g.plan, 5, True)
         torch.cuda.synchronize()
         cp, cc = g.state()
+        b.mxs_ch_set_step_mode(g.plan, b.MXS_CH_FUSED if mode == "fused" else b.MXS_CH_SEPARATE)
         b.mxs_ch_step(g.plan, 1, False)
         torch.cuda.synchronize()
         _, got = g.state()
@@ -279,7 +284,7 @@ def test_ch_reduced_precision_one_step_derived_bound(dt_name, shape):
     u32, us = 2.0 ** -24, {"f32": 2.0 ** -24, "bf16": 2.0 ** -8}[dt_name]
     bound = 2 * us * np.abs(ref) + LINV ** 2 * (32 + 2) * u32 * s_max
     err = np.abs(got - ref)
-    print(f"{dt_name} {shape}: max |dC| {err.max():.3e}, max of |dC| / bound {(err / bound).max():.3f}, "
+    print(f"{mode} {dt_name} {shape}: max |dC| {err.max():.3e}, max of |dC| / bound {(err / bound).max():.3f}, "
           f"cells differing by more than the arithmetic term {np.mean(err > LINV ** 2 * 34 * u32 * s_max):.2e}")
     assert np.all(err <= bound)
 
@@ -370,8 +375,8 @@ def test_autotune_keeps_the_state_and_parity():
     """Tuning times whole steps without advancing: the step count and both
     time levels are unchanged, the graphs captured before tuning are not
     replayed after it (the tables they point at are rebuilt), and graph
-    steps after tuning match eager steps of an untuned twin bit for bit and
-    the oracle to 1e-12."""
+    steps after tuning match eager steps of an untuned twin in the step form
+    the tuning chose bit for bit, and the oracle to 1e-12."""
     c0 = wl.ch_initial(72, 96, seed=21)
     g, twin = Grid(c0), Grid(c0)
     try:
@@ -384,6 +389,10 @@ def test_autotune_keeps_the_state_and_parity():
         assert b.mxs_ch_steps_taken(g.plan) == 4
         after = g.state()
         assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+        info = b.mxs_plan_info(g.plan)
+        form = info.split("step=")[1].split()[0]
+        b.mxs_ch_set_step_mode(twin.plan, {"separate": b.MXS_CH_SEPARATE, "persistent": b.MXS_CH_PERSISTENT,
+                                           "fused": b.MXS_CH_FUSED}[form])
         for k in range(4):
             b.mxs_ch_step(g.plan, 1, True)
             b.mxs_ch_step(twin.plan, 1, False)
@@ -592,9 +601,105 @@ def test_autotune_times_both_step_forms():
     try:
         b.mxs_autotune(plan)
         info = b.mxs_plan_info(plan)
-        assert "tuned_us_separate=" in info and "tuned_us_persistent=" in info
+        assert "tuned_us_separate=" in info and "tuned_us_persistent=" in info and "tuned_us_fused=" in info
         b.mxs_ch_step(plan, 4, True)
         torch.cuda.synchronize()
         b.mxs_ch_mass(plan, 5)
     finally:
         b.mxs_destroy(plan)
+
+
+# every register class of rows (1, 2, 4, 8 and 16 blocks of 256), row counts
+# that are and are not multiples of the four rows of a fused workgroup
+FUSED_SIZES = [(64, 64), (37, 300), (40, 600), (24, 1000), (21, 2048), (13, 4096), (40, 72), (9, 250)]
+
+
+@pytest.mark.parametrize("use_graph,rows", [(False, 4), (True, 4), (True, 8)])
+def test_fused_step_f64_matches_oracle(use_graph, rows, monkeypatch):
+    """The right-hand side formed inside the row solves, FP64 ensemble over
+    every register class, eager and graph-replayed, beside the separate
+    launches: both against the oracle per instance, within 1e-12 of max |C|
+    or twice the oracle's own rounding spread (its run with every window
+    weight and band value rounded one ulp the other way), whichever is
+    larger.  On the long, flat grids here (dx far below dy) the 13-point
+    weights of the x direction are large, and that spread reaches 1.3e-12
+    (21 x 2048) and 5.3e-12 (13 x 4096) of max |C| after 12 steps.  The
+    plan reports the fused form with one launch per class of rows and the
+    three column phases.  Workgroups of 4 and of 8 rows."""
+    monkeypatch.setenv("MXS_CH_FUSED_ROWS", str(rows))
+    nsteps = 12
+    got, info = {}, {}
+    for mode, key in ((b.MXS_CH_FUSED, "fused"), (b.MXS_CH_SEPARATE, "separate")):
+        plan, bufs, c0s, dxs, dys, dts = ensemble(FUSED_SIZES, "f64")
+        try:
+            b.mxs_ch_set_step_mode(plan, mode)
+            info[key] = b.mxs_plan_info(plan)
+            b.mxs_ch_step(plan, nsteps, use_graph)
+            torch.cuda.synchronize()
+            b.mxs_ch_mass(plan, len(FUSED_SIZES))
+            got[key] = currents(plan, bufs)
+        finally:
+            b.mxs_destroy(plan)
+    assert "step=fused launches_per_step=8 " in info["fused"], info   # 5 classes + 3 column phases
+    assert f"fused_rows={rows}" in info["fused"], info
+    for k, c0 in enumerate(c0s):
+        _, oc = oracle.ch_run(c0, c0, nsteps, dxs[k], dys[k], dts[k], D, GAMMA)
+        _, on = oracle.ch_run_nudged(c0, c0, nsteps, dxs[k], dys[k], dts[k], 1, D, GAMMA)
+        spread = np.abs(on - oc).max()
+        bound = max(1e-12 * np.abs(oc).max(), 2 * spread)
+        for key in ("fused", "separate"):
+            err = np.abs(got[key][k] - oc).max()
+            print(f"{key} {FUSED_SIZES[k]}: |GPU - oracle| {err:.3e}, oracle spread {spread:.3e}, "
+                  f"bound {bound:.3e}")
+            assert err <= bound, (key, k, FUSED_SIZES[k])
+
+
+@pytest.mark.parametrize("rows", [4, 8])
+@pytest.mark.parametrize("dt_name", ["f32", "bf16"])
+def test_fused_step_reduced_precision_matches_separate(dt_name, rows, monkeypatch):
+    """FP32 and BF16 storage over every register class: from the same state
+    (three separate steps), one fused step against one separate step.  The
+    two differ only by the float arithmetic of their right-hand sides (each
+    at most 32 float roundings of the per-point term sum S, carried through
+    two solves of infinity norm below LINV), a one-float-ulp difference in
+    w, and a one-ulp difference in each rounding to the storage dtype:
+    |dC| <= 4 u_s |C| + LINV^2 (2 * 32 + 2) u_32 max S.  Workgroups of 4
+    and of 8 rows."""
+    monkeypatch.setenv("MXS_CH_FUSED_ROWS", str(rows))
+    runs, states = [], []
+    for mode in (b.MXS_CH_SEPARATE, b.MXS_CH_FUSED):
+        plan, bufs, c0s, dxs, dys, dts = ensemble(FUSED_SIZES, dt_name)
+        try:
+            b.mxs_ch_step(plan, 3, True)
+            torch.cuda.synchronize()
+            if mode == b.MXS_CH_FUSED:
+                for k, q in enumerate(bufs):
+                    p_, c_ = b.mxs_ch_state(plan, k)
+                    states.append((ptr_tensor(p_, q).double().cpu().numpy(), ptr_tensor(c_, q).double().cpu().numpy()))
+            b.mxs_ch_set_step_mode(plan, mode)
+            b.mxs_ch_step(plan, 1, False)
+            torch.cuda.synchronize()
+            runs.append(currents(plan, bufs))
+        finally:
+            b.mxs_destroy(plan)
+    u32, us = 2.0 ** -24, {"f32": 2.0 ** -24, "bf16": 2.0 ** -8}[dt_name]
+    for k, (a, f) in enumerate(zip(*runs)):
+        cp, cc = states[k]
+        s_max = rhs_term_bound(cp, cc, dxs[k], dys[k], dts[k]).max()
+        bound = 4 * us * np.maximum(np.abs(a), np.abs(f)) + LINV ** 2 * (2 * 32 + 2) * u32 * s_max
+        err = np.abs(a - f)
+        print(f"{dt_name} {FUSED_SIZES[k]}: max |fused - separate| {err.max():.3e}, max ratio {(err / bound).max():.3f}")
+        assert np.all(err <= bound), k
+
+
+def test_fused_step_mode_errors():
+    g = Grid(wl.ch_initial(16, 64, seed=3))
+    try:
+        b.mxs_ch_set_step_mode(g.plan, b.MXS_CH_FUSED)
+        assert "step=fused" in b.mxs_plan_info(g.plan)
+        b.mxs_ch_set_step_mode(g.plan, b.MXS_CH_SEPARATE)
+        assert "step=separate" in b.mxs_plan_info(g.plan)
+        b.mxs_ch_step(g.plan, 2, True)
+        b.mxs_ch_mass(g.plan)
+    finally:
+        g.close()
