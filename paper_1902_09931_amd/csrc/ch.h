@@ -38,16 +38,18 @@ hipError_t launch_ch_rhs(int state_dtype, const RhsInst *inst, const int *map, i
                          int threads, hipStream_t s);
 
 // The right-hand side formed inside the row solves (chrows.hip): one
-// workgroup of wr wavefronts (wr = 4 or 8) per group of wr consecutive rows
-// of one instance, work[b] naming the instance and first row of group b.
-// One launch per register class nb of the rows (wave_nb of nx); R is never
-// stored and each wavefront writes w of its row through rows[inst].out.
+// workgroup of wr wavefronts per group of wr consecutive rows of one
+// instance, work[b] naming the instance and first row of group b, cpt
+// columns per thread and sub-block; shapes (wr, cpt) = (4, 1), (8, 1) or
+// (4, 2).  One launch per register class nb of the rows (wave_nb of nx); R is
+// never stored and each wavefront writes w of its row through rows[inst].out.
+// ch_rhs_rows_lds_bytes returns 0 for a shape that does not exist.
 struct RowsInst;
 struct RowGroup {
     int inst, j0;
 };
-size_t ch_rhs_rows_lds_bytes(int state_dtype, int wr, int nb);
-hipError_t launch_ch_rhs_rows(int state_dtype, int wr, int nb, const RhsInst *rhs, const RowsInst *rows,
+size_t ch_rhs_rows_lds_bytes(int state_dtype, int wr, int cpt, int nb);
+hipError_t launch_ch_rhs_rows(int state_dtype, int wr, int cpt, int nb, const RhsInst *rhs, const RowsInst *rows,
                               const RowGroup *work, int count, hipStream_t s);
 
 // Mass: per-instance double sums of a state buffer.

@@ -102,11 +102,12 @@ struct CHPlan final : mxs_plan_s {
     // words (arrivals, generation, exits, error)
     bool persistent = false, persist_ok = false;
     // right-hand side formed inside the row solves (one launch per register
-    // class of rows over groups of fused_rows rows, 4 or 8): eligible when
+    // class of rows over groups of fused_rows rows, fused_cols columns per
+    // thread and sub-block; shapes (4, 1), (8, 1), (4, 2)): eligible when
     // every row fits a register class; fused_work lists the row groups,
     // class by class
     bool fused = false, fused_ok = false;
-    int fused_rows = 4;
+    int fused_rows = 4, fused_cols = 1;
     DevBuf fused_work;
     std::vector<RowRange> fused_ranges;
     std::vector<int> class_order;   // instances ordered by register class of their rows
@@ -188,7 +189,7 @@ struct CHPlan final : mxs_plan_s {
             hipError_t e = hipSuccess;
             const RowGroup *work = static_cast<const RowGroup *>(fused_work.ptr);
             for (size_t q = 0; q < fused_ranges.size() && e == hipSuccess; ++q)
-                e = launch_ch_rhs_rows(dtype, fused_rows, fused_ranges[q].nb,
+                e = launch_ch_rhs_rows(dtype, fused_rows, fused_cols, fused_ranges[q].nb,
                                        static_cast<const RhsInst *>(rhs_d[r].ptr), ri, work + fused_ranges[q].first,
                                        fused_ranges[q].count, s);
             if (e != hipSuccess) return e;
@@ -423,7 +424,7 @@ struct CHPlan final : mxs_plan_s {
             bool pers;
             double t;
             bool fus = false;
-            int fr = 4;   // rows per workgroup of the fused form
+            int fr = 4, fc = 1;   // rows per workgroup and columns per thread of the fused form
         };
         std::vector<Cand> cands;
         for (int threads : {256, 128, 64})
@@ -437,10 +438,14 @@ struct CHPlan final : mxs_plan_s {
         if (persist_ok)
             for (int rows : {4, 8, 16, 32}) cands.push_back({kPersistThreads, rows, row_nw, true, 1e30});
         // the right-hand side inside the row solves (no right-hand side tiles to shape)
-        if (fused_ok)
-            for (int fr : {4, 8})
-                if (ch_rhs_rows_lds_bytes(dtype, fr, wave_nb(max_nx)) <= static_cast<size_t>(device_lds_limit()))
-                    cands.push_back({kRhsThreads, 16, row_nw, false, 1e30, true, fr});
+        if (fused_ok) {
+            const int shapes[3][2] = {{4, 1}, {8, 1}, {4, 2}};
+            for (const auto &sh : shapes) {
+                const size_t lds = ch_rhs_rows_lds_bytes(dtype, sh[0], sh[1], wave_nb(max_nx));
+                if (lds > 0 && lds <= static_cast<size_t>(device_lds_limit()))
+                    cands.push_back({kRhsThreads, 16, row_nw, false, 1e30, true, sh[0], sh[1]});
+            }
+        }
         if (cands.empty()) return MXS_OK;
         for (int pass = 0; pass < 2; ++pass)
             for (Cand &c : cands) {
@@ -453,6 +458,7 @@ struct CHPlan final : mxs_plan_s {
                     hipError_t fe = build_fused(c.fr);
                     if (fe != hipSuccess) return hip_fail(fe, "row group table upload");
                 }
+                if (c.fus) fused_cols = c.fc;
                 set_row_waves(c.w);
                 const double t = time_launches([&] { return enqueue(r, s); }, s, 2, 10);
                 if (t < 0) {
@@ -486,6 +492,7 @@ struct CHPlan final : mxs_plan_s {
             hipError_t fe = build_fused(best->fus ? best->fr : 4);
             if (fe != hipSuccess) return hip_fail(fe, "row group table upload");
         }
+        fused_cols = best->fus ? best->fc : 1;
         rhs_threads = best->threads;
         return build_rhs(best->rows);
     }
@@ -511,7 +518,7 @@ struct CHPlan final : mxs_plan_s {
             n += snprintf(buf + n, len - n, " tuned_us_separate=%.1f", best_graph_t * 1e6);
         if (best_persist && n < len)
             n += snprintf(buf + n, len - n, " tuned_us_persistent=%.1f", best_persist_t * 1e6);
-        if (fused && n < len) n += snprintf(buf + n, len - n, " fused_rows=%d", fused_rows);
+        if (fused && n < len) n += snprintf(buf + n, len - n, " fused_rows=%d fused_cols=%d", fused_rows, fused_cols);
         if (best_fused_t < 1e29 && n < len)
             n += snprintf(buf + n, len - n, " tuned_us_fused=%.1f", best_fused_t * 1e6);
         if (row_ranges.empty() && n < len)
@@ -612,9 +619,13 @@ struct CHPlan final : mxs_plan_s {
         fused_ok = false;
         class_order = by_class;
         if (reg_rows) {
-            // rows per fused workgroup: 4 until tuned; MXS_CH_FUSED_ROWS=8 picks 8 (tests)
+            // fused shape: 4 rows, 1 column per thread until tuned;
+            // MXS_CH_FUSED_ROWS=8 or MXS_CH_FUSED_COLS=2 pick another (tests)
             const char *fr = getenv("MXS_CH_FUSED_ROWS");
-            hipError_t fe = build_fused(fr && atoi(fr) == 8 ? 8 : 4);
+            const char *fcol = getenv("MXS_CH_FUSED_COLS");
+            const bool r8 = fr && atoi(fr) == 8, c2 = fcol && atoi(fcol) == 2 && !r8;
+            fused_cols = c2 ? 2 : 1;
+            hipError_t fe = build_fused(r8 ? 8 : 4);
             if (fe != hipSuccess) return hip_fail(fe, "row group table upload");
             fused_ok = true;
         }

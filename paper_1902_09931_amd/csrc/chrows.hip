@@ -28,35 +28,40 @@ namespace mxs {
 
 namespace {
 
-// Geometry of a workgroup of WR rows: 64 WR threads, sub-blocks of 64 WR
-// columns (one per thread), WR + 4 input rows per sub-block, LDS rows with
-// two halo columns on each side.
-template <int WR> struct FusedShape {
-    static constexpr int SUB = 64 * WR;
+// Geometry of a workgroup of WR rows: 64 WR threads, sub-blocks of
+// 64 WR CPT columns (CPT columns per thread, 64 WR apart), WR + 4 input rows
+// per sub-block, LDS rows with two halo columns on each side.
+template <int WR, int CPT> struct FusedShape {
+    static constexpr int NT = 64 * WR;
+    static constexpr int SUB = NT * CPT;
     static constexpr int GIN = WR + 4;
     static constexpr int LW = SUB + 4;
+    // LDS values: Cbar on every input row, C^3 - C on the inner GIN - 2, and
+    // C^n - C^{n-1} on the WR output rows
+    static constexpr int VALS = GIN * LW + (GIN - 2) * LW + WR * SUB;
 };
 
-template <typename T, typename TW, int NB, int WR>
+template <typename T, typename TW, int NB, int WR, int CPT>
 __global__ void __launch_bounds__(64 * WR) ch_rhs_rows_kernel(const RhsInst *__restrict__ rhs,
                                                               const RowsInst *__restrict__ rows,
                                                               const RowGroup *__restrict__ work, int count) {
     using A = typename St<T>::acc;
-    using FS = FusedShape<WR>;
-    constexpr int SUB = FS::SUB, GIN = FS::GIN, LW = FS::LW;
+    using FS = FusedShape<WR, CPT>;
+    constexpr int NT = FS::NT, SUB = FS::SUB, GIN = FS::GIN, LW = FS::LW;
     constexpr int E = WaveShape<NB>::E, NBB = WaveShape<NB>::NBB;
     constexpr int BLK = 64 * E;
     constexpr int NST = (NBB * BLK + SUB - 1) / SUB;   // sub-blocks of the longest line of the class
     constexpr int MPS = SUB / 64;                       // columns per lane and sub-block
-    // Eight rows per workgroup hold twice the values per thread in flight;
-    // their next sub-block is not requested early (the registers would not
-    // fit beside the line), four rows' is.
-    constexpr bool PREFETCH = WR <= 4;
+    // With one column per thread and four rows the next sub-block is
+    // requested before the current one is staged; wider sub-blocks (or
+    // eight rows) hold as many values per thread in flight at once instead,
+    // and the registers of a second set would not fit beside the line.
+    constexpr bool PREFETCH = WR <= 4 && CPT == 1;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     A *lb = reinterpret_cast<A *>(smem_raw);   // Cbar           [GIN][LW]
-    A *lf = lb + GIN * LW;                     // C^3 - C        [GIN][LW]
-    A *ld = lf + GIN * LW;                     // C^n - C^{n-1}  [WR][SUB]
+    A *lf = lb + GIN * LW;                     // C^3 - C        [GIN - 2][LW], input rows 1 .. GIN - 2
+    A *ld = lf + (GIN - 2) * LW;               // C^n - C^{n-1}  [WR][SUB]
 
     const RowGroup g = work[xcd_tile(blockIdx.x, count)];
     const RhsInst &I = rhs[g.inst];
@@ -80,15 +85,20 @@ __global__ void __launch_bounds__(64 * WR) ch_rhs_rows_kernel(const RhsInst *__r
     // halo: thread t < 4 GIN loads halo slot h = t % 4 of input row t / 4
     const int hu = min(t >> 2, GIN - 1), hh = t & 3;
 
-    // request the values of sub-block st (columns SUB st ..)
-    auto load = [&](int st, A (&c)[GIN], A (&p)[GIN], A &hc, A &hp) __attribute__((always_inline)) {
+    // request the values of sub-block st (columns SUB st ..): column
+    // SUB st + t + NT j of every input row into c[u][j], p[u][j]
+    auto load = [&](int st, A (&c)[GIN][CPT], A (&p)[GIN][CPT], A &hc, A &hp) __attribute__((always_inline)) {
         const long long cb = static_cast<long long>(st) * SUB;
-        const long long col = wrap_fast(cb + t, nx);
+        long long col[CPT];
 #pragma unroll
-        for (int u = 0; u < GIN; ++u) {
-            c[u] = to_acc<T>(gld<T>(cur, roff[u] + col));
-            p[u] = to_acc<T>(gld<T>(prev, roff[u] + col));
-        }
+        for (int j = 0; j < CPT; ++j) col[j] = wrap_fast(cb + t + NT * j, nx);
+#pragma unroll
+        for (int u = 0; u < GIN; ++u)
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                c[u][j] = to_acc<T>(gld<T>(cur, roff[u] + col[j]));
+                p[u][j] = to_acc<T>(gld<T>(prev, roff[u] + col[j]));
+            }
         hc = A(0);
         hp = A(0);
         if (t < 4 * GIN) {
@@ -104,7 +114,8 @@ __global__ void __launch_bounds__(64 * WR) ch_rhs_rows_kernel(const RhsInst *__r
 #pragma unroll
         for (int k = 0; k < E; ++k) raw[c][k] = TW(0);
 
-    A c0[GIN], p0[GIN], c1[GIN], p1[GIN], hc0, hp0, hc1, hp1;
+    A c0[GIN][CPT], p0[GIN][CPT], c1[PREFETCH ? GIN : 1][CPT], p1[PREFETCH ? GIN : 1][CPT];
+    A hc0, hp0, hc1, hp1;
     load(0, c0, p0, hc0, hp0);
 #pragma unroll
     for (int st = 0; st < NST; ++st) {
@@ -112,19 +123,24 @@ __global__ void __launch_bounds__(64 * WR) ch_rhs_rows_kernel(const RhsInst *__r
         if (!PREFETCH && st > 0) load(st, c0, p0, hc0, hp0);
         __syncthreads();                  // the previous sub-block's LDS reads are done
 #pragma unroll
-        for (int u = 0; u < GIN; ++u) {
-            const A cv = c0[u], pv = p0[u];
-            lb[u * LW + 2 + t] = A(2) * cv - pv;
-            if (u >= 1 && u <= GIN - 2) lf[u * LW + 2 + t] = cv * cv * cv - cv;
-            if (u >= 2 && u < 2 + WR) ld[(u - 2) * SUB + t] = cv - pv;
-        }
+        for (int u = 0; u < GIN; ++u)
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const A cv = c0[u][j], pv = p0[u][j];
+                const int x = 2 + t + NT * j;
+                lb[u * LW + x] = A(2) * cv - pv;
+                if (u >= 1 && u <= GIN - 2) lf[(u - 1) * LW + x] = cv * cv * cv - cv;
+                if (u >= 2 && u < 2 + WR) ld[(u - 2) * SUB + t + NT * j] = cv - pv;
+            }
         if (t < 4 * GIN) {
-            const int slot = hu * LW + (hh < 2 ? hh : SUB + hh);
-            lb[slot] = A(2) * hc0 - hp0;
-            lf[slot] = hc0 * hc0 * hc0 - hc0;
+            const int slot = hh < 2 ? hh : SUB + hh;
+            lb[hu * LW + slot] = A(2) * hc0 - hp0;
+            if (hu >= 1 && hu <= GIN - 2) lf[(hu - 1) * LW + slot] = hc0 * hc0 * hc0 - hc0;
         }
         // the next sub-block's requests overlap this one's arithmetic
-        if (PREFETCH && st + 1 < NST && (st + 1) * SUB < nsub) load(st + 1, c1, p1, hc1, hp1);
+        if constexpr (PREFETCH) {
+            if (st + 1 < NST && (st + 1) * SUB < nsub) load(st + 1, c1, p1, hc1, hp1);
+        }
         __syncthreads();
 
 #pragma unroll
@@ -144,16 +160,18 @@ __global__ void __launch_bounds__(64 * WR) ch_rhs_rows_kernel(const RhsInst *__r
             for (int q = 0; q < 3; ++q)
 #pragma unroll
                 for (int pp = 0; pp < 3; ++pp)
-                    if (lap_tap(q, pp)) acc = fma(wl[q * 3 + pp], lf[(w + 1 + q) * LW + o + 1 + pp], acc);
+                    if (lap_tap(q, pp)) acc = fma(wl[q * 3 + pp], lf[(w + q) * LW + o + 1 + pp], acc);
             acc = fma(cdiff, ld[w * SUB + o], acc);
             raw[c][k] = static_cast<TW>(acc);
         }
         if constexpr (PREFETCH) {
 #pragma unroll
-            for (int u = 0; u < GIN; ++u) {
-                c0[u] = c1[u];
-                p0[u] = p1[u];
-            }
+            for (int u = 0; u < GIN; ++u)
+#pragma unroll
+                for (int j = 0; j < CPT; ++j) {
+                    c0[u][j] = c1[u][j];
+                    p0[u][j] = p1[u][j];
+                }
             hc0 = hc1;
             hp0 = hp1;
         }
@@ -173,63 +191,71 @@ __global__ void __launch_bounds__(64 * WR) ch_rhs_rows_kernel(const RhsInst *__r
     wave_solve<TW, 2, NB>(L, raw, stage);
 }
 
-template <typename T, typename TW, int WR>
+template <typename T, typename TW, int WR, int CPT>
 size_t lds_bytes_of(int nb) {
     using A = typename St<T>::acc;
-    using FS = FusedShape<WR>;
     const int E = nb <= 1 ? WaveShape<1>::E : nb <= 2 ? WaveShape<2>::E : WaveShape<4>::E;
-    const size_t rhs = (static_cast<size_t>(2) * FS::GIN * FS::LW + static_cast<size_t>(WR) * FS::SUB) * sizeof(A);
+    const size_t rhs = static_cast<size_t>(FusedShape<WR, CPT>::VALS) * sizeof(A);
     const size_t stage = static_cast<size_t>(WR) * 64 * (E + 16 / sizeof(TW)) * sizeof(TW);
     return rhs > stage ? rhs : stage;
 }
 
-template <typename T, typename TW, int NB, int WR>
+template <typename T, typename TW, int NB, int WR, int CPT>
 hipError_t launch_nb(const RhsInst *rhs, const RowsInst *rows, const RowGroup *work, int count, hipStream_t s) {
-    const size_t lds = lds_bytes_of<T, TW, WR>(NB);
-    hipLaunchKernelGGL((ch_rhs_rows_kernel<T, TW, NB, WR>), dim3(count), dim3(64 * WR), lds, s, rhs, rows,
+    const size_t lds = lds_bytes_of<T, TW, WR, CPT>(NB);
+    hipLaunchKernelGGL((ch_rhs_rows_kernel<T, TW, NB, WR, CPT>), dim3(count), dim3(64 * WR), lds, s, rhs, rows,
                        work, count);
     return hipGetLastError();
 }
 
-template <typename T, typename TW, int WR>
+template <typename T, typename TW, int WR, int CPT>
 hipError_t launch_t(int nb, const RhsInst *rhs, const RowsInst *rows, const RowGroup *work, int count,
                     hipStream_t s) {
     switch (nb) {
-    case 1: return launch_nb<T, TW, 1, WR>(rhs, rows, work, count, s);
-    case 2: return launch_nb<T, TW, 2, WR>(rhs, rows, work, count, s);
-    case 4: return launch_nb<T, TW, 4, WR>(rhs, rows, work, count, s);
-    case 8: return launch_nb<T, TW, 8, WR>(rhs, rows, work, count, s);
-    case 16: return launch_nb<T, TW, 16, WR>(rhs, rows, work, count, s);
+    case 1: return launch_nb<T, TW, 1, WR, CPT>(rhs, rows, work, count, s);
+    case 2: return launch_nb<T, TW, 2, WR, CPT>(rhs, rows, work, count, s);
+    case 4: return launch_nb<T, TW, 4, WR, CPT>(rhs, rows, work, count, s);
+    case 8: return launch_nb<T, TW, 8, WR, CPT>(rhs, rows, work, count, s);
+    case 16: return launch_nb<T, TW, 16, WR, CPT>(rhs, rows, work, count, s);
     default: return hipErrorInvalidValue;
     }
 }
 
+// Shapes: (rows per workgroup, columns per thread) = (4, 1), (8, 1), (4, 2).
 template <typename T, typename TW>
-hipError_t launch_wr(int wr, int nb, const RhsInst *rhs, const RowsInst *rows, const RowGroup *work, int count,
-                     hipStream_t s) {
-    if (wr == 4) return launch_t<T, TW, 4>(nb, rhs, rows, work, count, s);
-    if (wr == 8) return launch_t<T, TW, 8>(nb, rhs, rows, work, count, s);
+hipError_t launch_shape(int wr, int cpt, int nb, const RhsInst *rhs, const RowsInst *rows, const RowGroup *work,
+                        int count, hipStream_t s) {
+    if (wr == 4 && cpt == 1) return launch_t<T, TW, 4, 1>(nb, rhs, rows, work, count, s);
+    if (wr == 8 && cpt == 1) return launch_t<T, TW, 8, 1>(nb, rhs, rows, work, count, s);
+    if (wr == 4 && cpt == 2) return launch_t<T, TW, 4, 2>(nb, rhs, rows, work, count, s);
     return hipErrorInvalidValue;
+}
+
+template <typename T, typename TW>
+size_t lds_shape(int wr, int cpt, int nb) {
+    if (wr == 4 && cpt == 1) return lds_bytes_of<T, TW, 4, 1>(nb);
+    if (wr == 8 && cpt == 1) return lds_bytes_of<T, TW, 8, 1>(nb);
+    if (wr == 4 && cpt == 2) return lds_bytes_of<T, TW, 4, 2>(nb);
+    return 0;
 }
 
 }  // namespace
 
-size_t ch_rhs_rows_lds_bytes(int state_dtype, int wr, int nb) {
-    if (wr != 4 && wr != 8) return 0;
+size_t ch_rhs_rows_lds_bytes(int state_dtype, int wr, int cpt, int nb) {
     switch (state_dtype) {
-    case F64: return wr == 4 ? lds_bytes_of<double, double, 4>(nb) : lds_bytes_of<double, double, 8>(nb);
-    case F32: return wr == 4 ? lds_bytes_of<float, float, 4>(nb) : lds_bytes_of<float, float, 8>(nb);
-    default: return wr == 4 ? lds_bytes_of<bf16, float, 4>(nb) : lds_bytes_of<bf16, float, 8>(nb);
+    case F64: return lds_shape<double, double>(wr, cpt, nb);
+    case F32: return lds_shape<float, float>(wr, cpt, nb);
+    default: return lds_shape<bf16, float>(wr, cpt, nb);
     }
 }
 
-hipError_t launch_ch_rhs_rows(int state_dtype, int wr, int nb, const RhsInst *rhs, const RowsInst *rows,
+hipError_t launch_ch_rhs_rows(int state_dtype, int wr, int cpt, int nb, const RhsInst *rhs, const RowsInst *rows,
                               const RowGroup *work, int count, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     switch (state_dtype) {
-    case F64: return launch_wr<double, double>(wr, nb, rhs, rows, work, count, s);
-    case F32: return launch_wr<float, float>(wr, nb, rhs, rows, work, count, s);
-    case BF16: return launch_wr<bf16, float>(wr, nb, rhs, rows, work, count, s);
+    case F64: return launch_shape<double, double>(wr, cpt, nb, rhs, rows, work, count, s);
+    case F32: return launch_shape<float, float>(wr, cpt, nb, rhs, rows, work, count, s);
+    case BF16: return launch_shape<bf16, float>(wr, cpt, nb, rhs, rows, work, count, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -614,8 +614,8 @@ def test_autotune_times_both_step_forms():
 FUSED_SIZES = [(64, 64), (37, 300), (40, 600), (24, 1000), (21, 2048), (13, 4096), (40, 72), (9, 250)]
 
 
-@pytest.mark.parametrize("use_graph,rows", [(False, 4), (True, 4), (True, 8)])
-def test_fused_step_f64_matches_oracle(use_graph, rows, monkeypatch):
+@pytest.mark.parametrize("use_graph,rows,cols", [(False, 4, 1), (True, 4, 1), (True, 8, 1), (True, 4, 2)])
+def test_fused_step_f64_matches_oracle(use_graph, rows, cols, monkeypatch):
     """The right-hand side formed inside the row solves, FP64 ensemble over
     every register class, eager and graph-replayed, beside the separate
     launches: both against the oracle per instance, within 1e-12 of max |C|
@@ -625,8 +625,10 @@ def test_fused_step_f64_matches_oracle(use_graph, rows, monkeypatch):
     weights of the x direction are large, and that spread reaches 1.3e-12
     (21 x 2048) and 5.3e-12 (13 x 4096) of max |C| after 12 steps.  The
     plan reports the fused form with one launch per class of rows and the
-    three column phases.  Workgroups of 4 and of 8 rows."""
+    three column phases.  Every workgroup shape: 4 rows with 1 or 2 columns
+    per thread, 8 rows."""
     monkeypatch.setenv("MXS_CH_FUSED_ROWS", str(rows))
+    monkeypatch.setenv("MXS_CH_FUSED_COLS", str(cols))
     nsteps = 12
     got, info = {}, {}
     for mode, key in ((b.MXS_CH_FUSED, "fused"), (b.MXS_CH_SEPARATE, "separate")):
@@ -641,7 +643,7 @@ def test_fused_step_f64_matches_oracle(use_graph, rows, monkeypatch):
         finally:
             b.mxs_destroy(plan)
     assert "step=fused launches_per_step=8 " in info["fused"], info   # 5 classes + 3 column phases
-    assert f"fused_rows={rows}" in info["fused"], info
+    assert f"fused_rows={rows} fused_cols={cols}" in info["fused"], info
     for k, c0 in enumerate(c0s):
         _, oc = oracle.ch_run(c0, c0, nsteps, dxs[k], dys[k], dts[k], D, GAMMA)
         _, on = oracle.ch_run_nudged(c0, c0, nsteps, dxs[k], dys[k], dts[k], 1, D, GAMMA)
@@ -654,18 +656,19 @@ def test_fused_step_f64_matches_oracle(use_graph, rows, monkeypatch):
             assert err <= bound, (key, k, FUSED_SIZES[k])
 
 
-@pytest.mark.parametrize("rows", [4, 8])
+@pytest.mark.parametrize("rows,cols", [(4, 1), (8, 1), (4, 2)])
 @pytest.mark.parametrize("dt_name", ["f32", "bf16"])
-def test_fused_step_reduced_precision_matches_separate(dt_name, rows, monkeypatch):
+def test_fused_step_reduced_precision_matches_separate(dt_name, rows, cols, monkeypatch):
     """FP32 and BF16 storage over every register class: from the same state
     (three separate steps), one fused step against one separate step.  The
     two differ only by the float arithmetic of their right-hand sides (each
     at most 32 float roundings of the per-point term sum S, carried through
     two solves of infinity norm below LINV), a one-float-ulp difference in
     w, and a one-ulp difference in each rounding to the storage dtype:
-    |dC| <= 4 u_s |C| + LINV^2 (2 * 32 + 2) u_32 max S.  Workgroups of 4
-    and of 8 rows."""
+    |dC| <= 4 u_s |C| + LINV^2 (2 * 32 + 2) u_32 max S.  Every workgroup
+    shape."""
     monkeypatch.setenv("MXS_CH_FUSED_ROWS", str(rows))
+    monkeypatch.setenv("MXS_CH_FUSED_COLS", str(cols))
     runs, states = [], []
     for mode in (b.MXS_CH_SEPARATE, b.MXS_CH_FUSED):
         plan, bufs, c0s, dxs, dys, dts = ensemble(FUSED_SIZES, dt_name)
