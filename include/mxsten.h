@@ -322,7 +322,9 @@ mxs_status mxs_ch_coarsening_noalloc(mxs_plan plan, int k, double *s_out,
 /* Choose the plan's launch layout by measurement: candidate layouts (rows
  * per workgroup, tile order, threads per workgroup and streaming stores for
  * 2D stencils; wavefronts per line for lines solved in LDS, longer than
- * 4096 elements; right-hand-side chunk height and workgroup size for the
+ * 4096 elements; step form (separate launches, right-hand side inside the
+ * row solves, persistent) with its right-hand-side chunk height and
+ * workgroup size, or rows and columns per fused workgroup, for the
  * Cahn-Hilliard step) are each run a few times on the plan's own buffers
  * and the fastest is kept.  A stencil or solve plan writes its output
  * buffer while tuning (with correct results); a Cahn-Hilliard plan rewrites

@@ -186,7 +186,7 @@ struct Stencil2DPlan final : mxs_plan_s {
         if (const char *env = getenv("MXS_STENCIL_TILE")) {
             int r = 0, o = 0, t = 0, nt = 1, blk = 0, xs = 0;
             const int k = sscanf(env, "%d,%d,%d,%d,%d,%d", &r, &o, &t, &nt, &blk, &xs);
-            if (k >= 3 && r > 0 && (o == 0 || o == 1) && (t == 64 || t == 128 || t == 256) &&
+            if (k >= 3 && r > 0 && (o == 0 || o == 1 || o == 2) && (t == 64 || t == 128 || t == 256) &&
                 (blk == 0 || stencil2d_block_ok(nwx, nwy, blk)) &&
                 (xs == 0 || stencil2d_xshuffle_ok(dtype, nwx, nwy, a.L, a.R, blk)) &&
                 stencil2d_lds_bytes(dtype, nwx, nwy, t, blk, xs) <= static_cast<size_t>(device_lds_limit()))
@@ -295,7 +295,7 @@ mxs_status Stencil2DPlan::autotune(hipStream_t s) {
         if (rows > 2 * a.ny && rows > 2) continue;
         for (int nthreads : {256, 128}) {
             if (stencil2d_lds_bytes(dtype, nwx, nwy, nthreads, 0, 0) > lds_limit) continue;
-            for (int order : {1, 0})
+            for (int order : {1, 0, 2})
                 for (int nt : {1, 0}) cands.push_back({TunedLayout{rows, order, nthreads, nt, 0, 0}, 1e30});
         }
     }
@@ -306,7 +306,7 @@ mxs_status Stencil2DPlan::autotune(hipStream_t s) {
             if (xs && !stencil2d_xshuffle_ok(dtype, nwx, nwy, a.L, a.R, block)) continue;
             for (int nthreads : {256, 128}) {
                 if (stencil2d_lds_bytes(dtype, nwx, nwy, nthreads, block, xs) > lds_limit) continue;
-                for (int order : {1, 0})
+                for (int order : {1, 0, 2})
                     for (int nt : {1, 0})
                         cands.push_back({TunedLayout{block - nwy + 1, order, nthreads, nt, block, xs}, 1e30});
             }

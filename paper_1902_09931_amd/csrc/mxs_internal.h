@@ -240,7 +240,8 @@ struct Stencil2DArgs {
     int nstrips;            // column strips
     int vec_ok;             // 16-byte (8-byte for bf16) aligned rows
     int order;              // tile order: 0 = each XCD a contiguous run of row chunks
-                            // of one strip; 1 = row-major sweep (strips fastest)
+                            // of one strip; 1 = row-major sweep (strips fastest);
+                            // 2 = each XCD a contiguous band of chunks, row-major
     int nt_store;           // 1: non-temporal output stores
     int block_rows;         // 0: streaming form; 8 or 16: block form reading
                             // that many input rows per workgroup at once

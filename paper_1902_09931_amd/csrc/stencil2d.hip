@@ -24,6 +24,29 @@ namespace mxs {
 
 namespace {
 
+// Strip and chunk of this workgroup.  order 0: the workgroups of one XCD
+// take one contiguous range of tiles numbered strip by strip (a band of
+// strips, chunks top to bottom); order 2: the same ranges numbered chunk by
+// chunk (a band of chunks, strips left to right), so that horizontal
+// neighbours, which share x halo columns, and vertical ones, which share
+// rows, run on the same XCD at about the same time; order 1: workgroups in
+// launch order, chunk by chunk.
+__device__ __forceinline__ void tile_of(const Stencil2DArgs &a, int &strip, int &chunk) {
+    if (a.order == 1) {
+        chunk = blockIdx.x / a.nstrips;
+        strip = blockIdx.x - chunk * a.nstrips;
+        return;
+    }
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (a.order == 0) {
+        strip = tile / a.nchunks;
+        chunk = tile - strip * a.nchunks;
+    } else {
+        chunk = tile / a.nstrips;
+        strip = tile - chunk * a.nstrips;
+    }
+}
+
 template <int NWX, int V> constexpr int halo_pad() {
     return NWX > 1 ? ((NWX - 1 + V - 1) / V) * V : 0;
 }
@@ -71,14 +94,7 @@ __global__ void __launch_bounds__(256) stencil2d_kernel(const Stencil2DArgs a) {
     const int W = nt * V;
     const int rowlen = PAD + W + PAD;
     int strip, chunk;
-    if (a.order == 0) {
-        const int tile = xcd_tile(blockIdx.x, gridDim.x);
-        strip = tile / a.nchunks;
-        chunk = tile - strip * a.nchunks;
-    } else {
-        chunk = blockIdx.x / a.nstrips;
-        strip = blockIdx.x - chunk * a.nstrips;
-    }
+    tile_of(a, strip, chunk);
     const long long i0 = static_cast<long long>(strip) * W;
     const int j0 = chunk * a.rows;
     const int H = min(a.rows, a.ny - j0);
@@ -590,14 +606,7 @@ template <typename T, int NWX, int NWY, int GIN, bool XS>
 __global__ void __launch_bounds__(256) stencil2d_block_kernel(const Stencil2DArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int strip, chunk;
-    if (a.order == 0) {
-        const int tile = xcd_tile(blockIdx.x, gridDim.x);
-        strip = tile / a.nchunks;
-        chunk = tile - strip * a.nchunks;
-    } else {
-        chunk = blockIdx.x / a.nstrips;
-        strip = blockIdx.x - chunk * a.nstrips;
-    }
+    tile_of(a, strip, chunk);
     const long long W = static_cast<long long>(blockDim.x) * St<T>::V;
     // a strip whose vectors all lie inside the grid, aligned: vector loads only
     if (a.vec_ok && (strip + 1) * W <= a.nx)

@@ -290,7 +290,9 @@ LAYOUTS = ["2,1,256,1", "4,0,256,0", "8,1,128,1", "16,0,128,0", "64,1,256,1", "1
            "1,1,256,1,8", "1,0,128,0,8", "1,1,128,1,16", "1,0,256,0,16", "1,1,64,1,16",
            "1,1,256,1,12",
            # block form, x neighbours by lane shifts (sixth field; centred windows)
-           "1,1,256,1,8,1", "1,0,128,0,12,1", "1,1,64,1,16,1"]
+           "1,1,256,1,8,1", "1,0,128,0,12,1", "1,1,64,1,16,1",
+           # tile order 2 (a band of row chunks per XCD, row-major), both forms
+           "4,2,256,1", "16,2,128,0", "1,2,256,1,8", "1,2,128,0,16", "1,2,256,1,8,1"]
 LAYOUT_WINDOWS = [("X", (2, 2, 0, 0), None), ("Y", (0, 0, 2, 1), None), ("XY", (1, 2, 2, 1), None),
                   ("XY", (1, 1, 1, 1), wl.CUBIC_MINUS_LINEAR), ("XY", (2, 2, 1, 1), None)]
 
@@ -317,7 +319,7 @@ BLOCK_WINDOWS = [("Y", (0, 0, 1, 1)), ("Y", (0, 0, 2, 2)), ("Y", (0, 0, 3, 0)), 
 
 
 @pytest.mark.parametrize("layout", ["1,1,64,1,8", "1,0,128,0,16", "1,1,64,1,8,1", "1,0,256,0,12,1",
-                                    "1,1,128,1,16,1"])
+                                    "1,1,128,1,16,1", "1,2,128,1,8"])
 @pytest.mark.parametrize("shape", [(5, 9), (8, 70), (37, 45), (257, 129), (23, 1030)])
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
 def test_block_form_small_and_ragged_grids(monkeypatch, layout, shape, dt):
