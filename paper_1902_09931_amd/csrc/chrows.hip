@@ -5,16 +5,17 @@
 //
 // Cbar = 2 C^n - C^{n-1} (the terms as in ch.h).  A workgroup of WR
 // wavefronts (WR = 4 or 8) takes WR consecutive rows of one instance.  The
-// rows are walked in sub-blocks of 64 WR columns: for each, every thread
-// requests one column of the WR + 4 input rows of C^n and C^{n-1} the rows'
-// windows reach (periodic in both directions; two halo columns on each side
-// from 4 (WR + 4) threads), the workgroup stages Cbar, C^n^3 - C^n and
-// C^n - C^{n-1} in LDS, and each wavefront forms R of its own row at the
-// sub-block's columns, directly in the register layout the line solver
-// starts from (element BLK c + 64 k + lane of the line in raw[c][k] of lane
-// `lane`).  With four rows the next sub-block's values are requested before
-// the current one is staged.  Then every wavefront solves its row in
-// registers (the register line solver of wave_dev.h) and stores w.
+// rows are walked in sub-blocks of 64 WR CPT columns (CPT = 1 or 2 columns
+// per thread): for each, every thread requests its columns of the WR + 4
+// input rows of C^n and C^{n-1} the rows' windows reach (periodic in both
+// directions; two halo columns on each side from 4 (WR + 4) threads), the
+// workgroup stages Cbar, C^n^3 - C^n and C^n - C^{n-1} in LDS, and each
+// wavefront forms R of its own row at the sub-block's columns, directly in
+// the register layout the line solver starts from (element BLK c + 64 k +
+// lane of the line in raw[c][k] of lane `lane`).  With four rows and one
+// column per thread the next sub-block's values are requested before the
+// current one is staged.  Then every wavefront solves its row in registers
+// (the register line solver of wave_dev.h) and stores w.
 //
 // Memory: C^n and C^{n-1} are read once per workgroup, WR + 4 rows for WR
 // rows of output; the 4 rows a workgroup shares with its neighbours come from
