@@ -13,7 +13,7 @@ updated per second (8 x 8192^2 per step).
 The JSON line also carries the roofline of the dominant kernel (its average
 launch time taken with HIP events on the stream it runs on, against the
 algorithmic 16 bytes per point), the oracle timed on the host cores on a
-bounded sample, and further sections under "extra": the FP32 stencil set,
+bounded sample, and further sections under "extra": the FP32 and BF16 stencil sets,
 batched ragged 1D stencils and cyclic tridiagonal solves (65536 lines), the
 ADI Cahn-Hilliard step on 1024^2 and 4096^2 FP64 grids (steps/s), the
 64-grid FP32/BF16 ensemble against the FP64 path, the WENO advection
@@ -84,10 +84,10 @@ def bench_stencil_set(torch, b, wl, n, dt, steps, warmup):
     Inputs and outputs rotate over enough buffer pairs (>= 2 GiB) that
     consecutive launches never find their data in the 256 MB MALL.
     Returns (s per step, wall s per step, per-kernel s, count, layouts)."""
-    tdt = {"f64": torch.float64, "f32": torch.float32}[dt]
-    code = {"f64": b.MXS_F64, "f32": b.MXS_F32}[dt]
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dt]
+    code = {"f64": b.MXS_F64, "f32": b.MXS_F32, "bf16": b.MXS_BF16}[dt]
     dirs = {"X": b.MXS_X, "Y": b.MXS_Y, "XY": b.MXS_XY}
-    esz = 8 if dt == "f64" else 4
+    esz = {"f64": 8, "f32": 4, "bf16": 2}[dt]
     npairs = max(2, (2 << 30) // (2 * esz * n * n))
     u0 = torch.from_numpy(wl.uniform_grid(n, n, seed=1)).to(tdt).cuda()
     ins = [u0] + [u0.clone() for _ in range(npairs - 1)]
@@ -608,7 +608,7 @@ def main():
                     help="time the oracle on the stencil set and the 1024^2 CH step only")
     ap.add_argument("--sections-only", action="store_true",
                     help="skip the headline stencil set (for profiling the sections)")
-    ap.add_argument("--sections", default="f32,ragged,tri,weno,ch,ensemble,copy",
+    ap.add_argument("--sections", default="f32,bf16,ragged,tri,weno,ch,ensemble,copy",
                     help="extra sections to run (comma list)")
     ap.add_argument("--ch-steps", type=int, default=0,
                     help="override the Cahn-Hilliard step counts (0: 1000 at 1024^2, 200 at 4096^2)")
@@ -673,14 +673,16 @@ def main():
              "f64_kernels_us": {k: v * 1e6 for k, v in per_kernel.items()},
              "f64_hbm_frac_per_kernel": {k: bytes_per_launch / v / 1e9 / HBM_PEAK_GBS
                                          for k, v in per_kernel.items()}}
-    if "f32" in sections:
-        log("stencil set f32")
-        s32, _, pk32, _, lay32 = bench_stencil_set(torch, b, wl, n, "f32", args.steps, args.warmup)
-        extra["f32_layouts"] = lay32
-        extra["f32_gpoints_per_s"] = pts / s32 / 1e9
-        extra["f32_kernels_us"] = {k: v * 1e6 for k, v in pk32.items()}
-        extra["f32_hbm_frac_per_kernel"] = {k: 2 * 4 * n * n / v / 1e9 / HBM_PEAK_GBS
-                                            for k, v in pk32.items()}
+    # reduced-precision storage (FP32 accumulation): the same set in FP32 and BF16
+    for dt, esz in (("f32", 4), ("bf16", 2)):
+        if dt in sections:
+            log(f"stencil set {dt}")
+            sr, _, pkr, _, layr = bench_stencil_set(torch, b, wl, n, dt, args.steps, args.warmup)
+            extra[f"{dt}_layouts"] = layr
+            extra[f"{dt}_gpoints_per_s"] = pts / sr / 1e9
+            extra[f"{dt}_kernels_us"] = {k: v * 1e6 for k, v in pkr.items()}
+            extra[f"{dt}_hbm_frac_per_kernel"] = {k: 2 * esz * n * n / v / 1e9 / HBM_PEAK_GBS
+                                                  for k, v in pkr.items()}
     for dt in ("f64", "f32"):
         if "ragged" in sections:
             log(f"ragged 1D stencil {dt}")

@@ -30,7 +30,7 @@ inline int dtype_size(int dt) { return dt == F64 ? 8 : dt == F32 ? 4 : 2; }
 template <typename T> struct St;
 template <> struct St<double> { using acc = double; static constexpr int V = 2; };
 template <> struct St<float>  { using acc = float;  static constexpr int V = 4; };
-template <> struct St<bf16>   { using acc = float;  static constexpr int V = 4; };
+template <> struct St<bf16>   { using acc = float;  static constexpr int V = 8; };
 
 __device__ __forceinline__ float bf16_to_float(uint16_t b) {
     return __uint_as_float(static_cast<uint32_t>(b) << 16);
@@ -55,8 +55,8 @@ template <> __device__ __forceinline__ double from_acc<double>(double v) { retur
 template <> __device__ __forceinline__ float from_acc<float>(float v) { return v; }
 template <> __device__ __forceinline__ bf16 from_acc<bf16>(float v) { return bf16{float_to_bf16(v)}; }
 
-// Vector load/store of St<T>::V consecutive elements (16 bytes for double and
-// float, 8 bytes for bf16).  The address must be aligned to the vector size.
+// Vector load/store of St<T>::V consecutive elements (16 bytes: 2 doubles, 4
+// floats or 8 bfloat16s).  The address must be aligned to 16 bytes.
 template <typename T>
 __device__ __forceinline__ void load_vec(const T *p, typename St<T>::acc *x);
 template <>
@@ -69,11 +69,24 @@ __device__ __forceinline__ void load_vec<float>(const float *p, float *x) {
     float4 v = *reinterpret_cast<const float4 *>(p);
     x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
 }
+// 8 bfloat16s from / to 4 packed words
+__device__ __forceinline__ void unpack_bf16x8(const uint32_t (&w)[4], float *x) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        x[2 * k] = __uint_as_float(w[k] << 16);
+        x[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+    }
+}
+__device__ __forceinline__ void pack_bf16x8(const float *x, uint32_t (&w)[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        w[k] = static_cast<uint32_t>(float_to_bf16(x[2 * k])) | (static_cast<uint32_t>(float_to_bf16(x[2 * k + 1])) << 16);
+}
 template <>
 __device__ __forceinline__ void load_vec<bf16>(const bf16 *p, float *x) {
-    uint2 v = *reinterpret_cast<const uint2 *>(p);
-    x[0] = __uint_as_float(v.x << 16); x[1] = __uint_as_float(v.x & 0xffff0000u);
-    x[2] = __uint_as_float(v.y << 16); x[3] = __uint_as_float(v.y & 0xffff0000u);
+    const uint4 v = *reinterpret_cast<const uint4 *>(p);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    unpack_bf16x8(w, x);
 }
 
 template <typename T>
@@ -88,10 +101,9 @@ __device__ __forceinline__ void store_vec<float>(float *p, const float *x) {
 }
 template <>
 __device__ __forceinline__ void store_vec<bf16>(bf16 *p, const float *x) {
-    uint2 v;
-    v.x = static_cast<uint32_t>(float_to_bf16(x[0])) | (static_cast<uint32_t>(float_to_bf16(x[1])) << 16);
-    v.y = static_cast<uint32_t>(float_to_bf16(x[2])) | (static_cast<uint32_t>(float_to_bf16(x[3])) << 16);
-    *reinterpret_cast<uint2 *>(p) = v;
+    uint32_t w[4];
+    pack_bf16x8(x, w);
+    *reinterpret_cast<uint4 *>(p) = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
 // Streaming (non-temporal) vector stores: the line is written without being
@@ -114,9 +126,10 @@ __device__ __forceinline__ void store_vec_nt<float>(float *p, const float *x) {
 }
 template <>
 __device__ __forceinline__ void store_vec_nt<bf16>(bf16 *p, const float *x) {
-    v2u_t v = {static_cast<uint32_t>(float_to_bf16(x[0])) | (static_cast<uint32_t>(float_to_bf16(x[1])) << 16),
-               static_cast<uint32_t>(float_to_bf16(x[2])) | (static_cast<uint32_t>(float_to_bf16(x[3])) << 16)};
-    __builtin_nontemporal_store(v, reinterpret_cast<v2u_t *>(p));
+    uint32_t w[4];
+    pack_bf16x8(x, w);
+    v4u_t v = {w[0], w[1], w[2], w[3]};
+    __builtin_nontemporal_store(v, reinterpret_cast<v4u_t *>(p));
 }
 
 // Element access through global-memory pointers (bf16 by its bits).
@@ -144,9 +157,9 @@ __device__ __forceinline__ void load_vec<float>(gptr<const float> p, float *x) {
 }
 template <>
 __device__ __forceinline__ void load_vec<bf16>(gptr<const bf16> p, float *x) {
-    const v2u_t v = *reinterpret_cast<gptr<const v2u_t>>(p);
-    x[0] = __uint_as_float(v.x << 16); x[1] = __uint_as_float(v.x & 0xffff0000u);
-    x[2] = __uint_as_float(v.y << 16); x[3] = __uint_as_float(v.y & 0xffff0000u);
+    const v4u_t v = *reinterpret_cast<gptr<const v4u_t>>(p);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    unpack_bf16x8(w, x);
 }
 template <typename T>
 __device__ __forceinline__ void store_vec(gptr<T> p, const typename St<T>::acc *x);
@@ -162,9 +175,10 @@ __device__ __forceinline__ void store_vec<float>(gptr<float> p, const float *x) 
 }
 template <>
 __device__ __forceinline__ void store_vec<bf16>(gptr<bf16> p, const float *x) {
-    const v2u_t v = {static_cast<uint32_t>(float_to_bf16(x[0])) | (static_cast<uint32_t>(float_to_bf16(x[1])) << 16),
-                     static_cast<uint32_t>(float_to_bf16(x[2])) | (static_cast<uint32_t>(float_to_bf16(x[3])) << 16)};
-    *reinterpret_cast<gptr<v2u_t>>(p) = v;
+    uint32_t w[4];
+    pack_bf16x8(x, w);
+    const v4u_t v = {w[0], w[1], w[2], w[3]};
+    *reinterpret_cast<gptr<v4u_t>>(p) = v;
 }
 template <typename T>
 __device__ __forceinline__ void store_vec_nt(gptr<T> p, const typename St<T>::acc *x);
@@ -180,9 +194,10 @@ __device__ __forceinline__ void store_vec_nt<float>(gptr<float> p, const float *
 }
 template <>
 __device__ __forceinline__ void store_vec_nt<bf16>(gptr<bf16> p, const float *x) {
-    v2u_t v = {static_cast<uint32_t>(float_to_bf16(x[0])) | (static_cast<uint32_t>(float_to_bf16(x[1])) << 16),
-               static_cast<uint32_t>(float_to_bf16(x[2])) | (static_cast<uint32_t>(float_to_bf16(x[3])) << 16)};
-    __builtin_nontemporal_store(v, reinterpret_cast<gptr<v2u_t>>(p));
+    uint32_t w[4];
+    pack_bf16x8(x, w);
+    v4u_t v = {w[0], w[1], w[2], w[3]};
+    __builtin_nontemporal_store(v, reinterpret_cast<gptr<v4u_t>>(p));
 }
 
 __device__ __forceinline__ long long wrap_ll(long long k, long long n) {
@@ -238,7 +253,7 @@ struct Stencil2DArgs {
     int rows;               // output rows per workgroup
     int nchunks;            // row chunks per strip
     int nstrips;            // column strips
-    int vec_ok;             // 16-byte (8-byte for bf16) aligned rows
+    int vec_ok;             // 16-byte aligned rows
     int order;              // tile order: 0 = each XCD a contiguous run of row chunks
                             // of one strip; 1 = row-major sweep (strips fastest);
                             // 2 = each XCD a contiguous band of chunks, row-major
