@@ -37,10 +37,43 @@ template <int WR, int CPT> struct FusedShape {
     static constexpr int SUB = NT * CPT;
     static constexpr int GIN = WR + 4;
     static constexpr int LW = SUB + 4;
-    // LDS values: Cbar on every input row, C^3 - C on the inner GIN - 2, and
-    // C^n - C^{n-1} on the WR output rows
-    static constexpr int VALS = GIN * LW + (GIN - 2) * LW + WR * SUB;
+    // LDS values: Cbar on every input row, C^3 - C on the inner GIN - 2,
+    // C^n - C^{n-1} on the WR output rows, and 256 values of R per wavefront
+    static constexpr int VALS = GIN * LW + (GIN - 2) * LW + WR * SUB + WR * 256;
 };
+
+// N consecutive values from LDS at a 16-byte aligned address, by 16-byte reads.
+template <typename A, int N> __device__ __forceinline__ void lds_read(const A *p, A *x) {
+    constexpr int PER = 16 / static_cast<int>(sizeof(A));
+    static_assert(N % PER == 0, "whole 16-byte vectors");
+#pragma unroll
+    for (int k = 0; k < N; k += PER) {
+        if constexpr (PER == 2) {
+            const v2d_t v = *reinterpret_cast<const v2d_t *>(p + k);
+            x[k] = v.x;
+            x[k + 1] = v.y;
+        } else {
+            const v4f_t v = *reinterpret_cast<const v4f_t *>(p + k);
+            x[k] = v.x;
+            x[k + 1] = v.y;
+            x[k + 2] = v.z;
+            x[k + 3] = v.w;
+        }
+    }
+}
+
+// The slots [s0, s0 + n) a lane reads from an LDS row for taps lo..hi of its
+// four outputs (output i, tap p at slot i + p + shift), widened to whole
+// 16-byte vectors.
+struct SlotRange {
+    int s0, n;
+};
+template <typename A> constexpr SlotRange slot_range(int lo, int hi, int shift) {
+    const int per = 16 / static_cast<int>(sizeof(A));
+    const int first = lo + shift, last = 3 + hi + shift;
+    const int s0 = first / per * per;
+    return SlotRange{s0, (last + 1 - s0 + per - 1) / per * per};
+}
 
 template <typename T, typename TW, int NB, int WR, int CPT>
 __global__ void __launch_bounds__(64 * WR) ch_rhs_rows_kernel(const RhsInst *__restrict__ rhs,
@@ -52,7 +85,6 @@ __global__ void __launch_bounds__(64 * WR) ch_rhs_rows_kernel(const RhsInst *__r
     constexpr int E = WaveShape<NB>::E, NBB = WaveShape<NB>::NBB;
     constexpr int BLK = 64 * E;
     constexpr int NST = (NBB * BLK + SUB - 1) / SUB;   // sub-blocks of the longest line of the class
-    constexpr int MPS = SUB / 64;                       // columns per lane and sub-block
     // With one column per thread and four rows the next sub-block is
     // requested before the current one is staged; wider sub-blocks (or
     // eight rows) hold as many values per thread in flight at once instead,
@@ -144,26 +176,58 @@ __global__ void __launch_bounds__(64 * WR) ch_rhs_rows_kernel(const RhsInst *__r
         }
         __syncthreads();
 
+        // each lane forms R at 4 consecutive columns of every 256 (ob .. ob
+        // + 3), reading every window row once with 16-byte reads, and the
+        // wavefront moves the values to the line solver's layout (column
+        // 64 m + lane) through 256 LDS words of its own
+        A *ws = ld + WR * SUB + w * 256;
 #pragma unroll
-        for (int m = 0; m < MPS; ++m) {
-            // column SUB st + 64 m + lane of the line: element BLK c + 64 k + lane
-            const int x0 = st * SUB + 64 * m;   // compile time after unrolling
-            const int c = x0 / BLK, k = (x0 % BLK) / 64;
-            if (c >= NBB) continue;
-            const int o = 64 * m + lane;   // column within the sub-block
-            A acc = A(0);
+        for (int gq = 0; gq < SUB / 256; ++gq) {
+            const int ob = 256 * gq + 4 * lane;
+            A acc[4] = {A(0), A(0), A(0), A(0)};
 #pragma unroll
-            for (int q = 0; q < 5; ++q)
+            for (int q = 0; q < 5; ++q) {
+                const int plo = (q == 0 || q == 4) ? 2 : (q == 1 || q == 3) ? 1 : 0;
+                constexpr SlotRange r0 = slot_range<A>(2, 2, 0), r1 = slot_range<A>(1, 3, 0),
+                                    r2 = slot_range<A>(0, 4, 0);
+                const SlotRange r = plo == 2 ? r0 : plo == 1 ? r1 : r2;
+                A x[8];
+                if (r.n == 4) lds_read<A, 4>(lb + (w + q) * LW + ob + r.s0, x);
+                else lds_read<A, 8>(lb + (w + q) * LW + ob + r.s0, x);
 #pragma unroll
-                for (int pp = 0; pp < 5; ++pp)
-                    if (bih_tap(q, pp)) acc = fma(wb[q * 5 + pp], lb[(w + q) * LW + o + pp], acc);
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int q = 0; q < 3; ++q)
+                    for (int pp = 0; pp < 5; ++pp)
+                        if (bih_tap(q, pp)) acc[i] = fma(wb[q * 5 + pp], x[i + pp - r.s0], acc[i]);
+            }
 #pragma unroll
-                for (int pp = 0; pp < 3; ++pp)
-                    if (lap_tap(q, pp)) acc = fma(wl[q * 3 + pp], lf[(w + q) * LW + o + 1 + pp], acc);
-            acc = fma(cdiff, ld[w * SUB + o], acc);
-            raw[c][k] = static_cast<TW>(acc);
+            for (int q = 0; q < 3; ++q) {
+                const int plo = q == 1 ? 0 : 1;
+                constexpr SlotRange r0 = slot_range<A>(1, 1, 1), r1 = slot_range<A>(0, 2, 1);
+                const SlotRange r = plo == 1 ? r0 : r1;
+                A x[8];
+                if (r.n == 4) lds_read<A, 4>(lf + (w + q) * LW + ob + r.s0, x);
+                else lds_read<A, 8>(lf + (w + q) * LW + ob + r.s0, x);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int pp = 0; pp < 3; ++pp)
+                        if (lap_tap(q, pp)) acc[i] = fma(wl[q * 3 + pp], x[i + pp + 1 - r.s0], acc[i]);
+            }
+            A dv[4];
+            lds_read<A, 4>(ld + w * SUB + ob, dv);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ws[4 * lane + i] = fma(cdiff, dv[i], acc[i]);
+            wave_sync();
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                // column SUB st + 256 gq + 64 m + lane of the line: element
+                // BLK c + 64 k + lane
+                const int x0 = st * SUB + 256 * gq + 64 * m;   // compile time after unrolling
+                const int c = x0 / BLK, k = (x0 % BLK) / 64;
+                if (c < NBB) raw[c][k] = static_cast<TW>(ws[64 * m + lane]);
+            }
+            wave_sync();   // the reads are done before the next group's writes
         }
         if constexpr (PREFETCH) {
 #pragma unroll
