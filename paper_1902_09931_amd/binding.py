@@ -253,8 +253,8 @@ def mxs_autotune(plan, stream=None):
 
 
 def mxs_plan_info(plan):
-    buf = ctypes.create_string_buffer(256)
-    _check(_lib.mxs_plan_info(plan, buf, 256))
+    buf = ctypes.create_string_buffer(1024)
+    _check(_lib.mxs_plan_info(plan, buf, 1024))
     return buf.value.decode()
 
 

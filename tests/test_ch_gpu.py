@@ -609,9 +609,11 @@ def test_autotune_times_both_step_forms():
         b.mxs_destroy(plan)
 
 
-# every register class of rows (1, 2, 4, 8 and 16 blocks of 256), row counts
-# that are and are not multiples of the four rows of a fused workgroup
-FUSED_SIZES = [(64, 64), (37, 300), (40, 600), (24, 1000), (21, 2048), (13, 4096), (40, 72), (9, 250)]
+# every register class of rows (1, 2, 4, 8 and 16 blocks of 256, the last
+# with a full and a partial fourth block), row counts that are and are not
+# multiples of the four rows of a fused workgroup
+FUSED_SIZES = [(64, 64), (37, 300), (40, 600), (24, 1000), (21, 2048), (11, 3000), (13, 4096), (40, 72),
+               (9, 250)]
 
 
 @pytest.mark.parametrize("use_graph,rows,cols", [(False, 4, 1), (True, 4, 1), (True, 8, 1), (True, 4, 2)])
