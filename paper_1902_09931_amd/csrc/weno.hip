@@ -33,7 +33,7 @@ constexpr int kWenoPad = 4;   // halo columns staged on each side (3 used), a wh
 // squared difference plus 1e-99.
 //
 // Arithmetic: the candidates by multiplications with rounded constants
-// instead of divisions, and the weights with one division instead of four:
+// instead of divisions, and the weights with one quotient instead of four:
 // w_k = g_k prod_{m != k} d_m^2 / sum_l g_l prod_{m != l} d_m^2, d = s + eps,
 // the same ratio.  The d_m are first scaled by the same power of two
 // (exactly), so that the largest lies in [1/2, 1): since s_m <= 34 max v^2
@@ -52,8 +52,10 @@ __device__ __forceinline__ double weno5(double v1, double v2, double v3, double 
     a = v3 - 2.0 * v4 + v5;
     b = 3.0 * v3 - 4.0 * v4 + v5;
     const double s3 = fma(13.0 / 12.0, a * a, 0.25 * (b * b));
-    const double m = fmax(fmax(fmax(v1 * v1, v2 * v2), fmax(v3 * v3, v4 * v4)), v5 * v5);
-    const double eps = fma(1e-6, m, 1e-99);
+    // the largest square is the square of the largest magnitude (rounding
+    // of a square is monotone in |v|), one multiplication instead of five
+    const double va = fmax(fmax(fmax(fabs(v1), fabs(v2)), fmax(fabs(v3), fabs(v4))), fabs(v5));
+    const double eps = fma(1e-6, va * va, 1e-99);
     double d1 = s1 + eps, d2 = s2 + eps, d3 = s3 + eps;
     const int ex = __builtin_amdgcn_frexp_exp(fmax(fmax(d1, d2), d3));
     d1 = __builtin_amdgcn_ldexp(d1, -ex);
@@ -61,7 +63,16 @@ __device__ __forceinline__ double weno5(double v1, double v2, double v3, double 
     d3 = __builtin_amdgcn_ldexp(d3, -ex);
     const double q1 = d1 * d1, q2 = d2 * d2, q3 = d3 * d3;
     const double n1 = 0.1 * (q2 * q3), n2 = 0.6 * (q1 * q3), n3 = 0.3 * (q1 * q2);
-    return fma(n1, p1, fma(n2, p2, n3 * p3)) / (n1 + n2 + n3);
+    // num / den with the hardware reciprocal refined by two Newton steps and
+    // a final residual correction (den is a normal number in [4e-33, 1]
+    // after the scaling, so none of the special cases of a general division
+    // arise); within one rounding of the quotient
+    const double num = fma(n1, p1, fma(n2, p2, n3 * p3)), den = n1 + n2 + n3;
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(fma(-den, r, 1.0), r, r);
+    r = fma(fma(-den, r, 1.0), r, r);
+    const double q = num * r;
+    return fma(fma(-den, q, num), r, q);
 }
 
 // The upwind WENO derivative from seven consecutive values f[0..6] centred on
