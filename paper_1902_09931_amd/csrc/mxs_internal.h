@@ -268,7 +268,7 @@ struct Stencil2DArgs {
 // Vectors per thread in one tile of the batched 1D stencil (a tile is
 // threads * V * kS1dVecs elements, so one workgroup has that many bytes in
 // flight at once).
-constexpr int kS1dVecs = 2;
+constexpr int kS1dVecs = 4;
 
 struct Stencil1DArgs {
     const void *in;

@@ -241,7 +241,11 @@ def run_1d(vals, offsets, periodic, L, R, w, coe, dt, fill=float("nan")):
 @pytest.mark.parametrize("dt,fun", [("f64", False), ("f64", True), ("f32", False), ("bf16", True)])
 def test_stencil1d_ragged_parity(L, R, periodic, dt, fun):
     rng = np.random.default_rng(L * 100 + R)
-    lengths = rng.permutation([17, 18, 64, 65, 97, 200, 513, 1025, 4096, 19, 700, 31, 2049])
+    # three shuffles of a spread of lengths and a run of short signals (many
+    # signals per tile): several tiles of every dtype and a ragged tail
+    base = [17, 18, 64, 65, 97, 200, 513, 1025, 4096, 19, 700, 31, 2049]
+    lengths = np.concatenate([rng.permutation(base), rng.integers(17, 41, 600),
+                              rng.permutation(base), rng.permutation(base)])
     offs = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
     vals = rng.uniform(-1, 1, offs[-1])
     w = rng.uniform(-1, 1, L + R + 1)
