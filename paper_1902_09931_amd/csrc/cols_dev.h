@@ -28,6 +28,20 @@ __device__ __forceinline__ Aff compose(const Aff &hi, const Aff &lo) {
     return r;
 }
 
+// compose with each sum of products rounded as written (explicit fma), so
+// that the result does not depend on how the compiler contracts the code
+// around it: code paths that must agree bit for bit use this form
+__device__ __forceinline__ Aff compose_x(const Aff &hi, const Aff &lo) {
+    Aff r;
+    r.a = fma(hi.a, lo.a, hi.b * lo.c);
+    r.b = fma(hi.a, lo.b, hi.b * lo.d);
+    r.c = fma(hi.c, lo.a, hi.d * lo.c);
+    r.d = fma(hi.c, lo.b, hi.d * lo.d);
+    r.e0 = fma(hi.a, lo.e0, fma(hi.b, lo.e1, hi.e0));
+    r.e1 = fma(hi.c, lo.e0, fma(hi.d, lo.e1, hi.e1));
+    return r;
+}
+
 template <bool UP> __device__ __forceinline__ double shfl_step(double v, int d) {
     return UP ? __shfl_up(v, d, 64) : __shfl_down(v, d, 64);
 }
@@ -147,14 +161,18 @@ __device__ __forceinline__ void cols_a_block(const ColsInst *__restrict__ inst, 
 // affine maps of its segments, the groups of a column combine their maps
 // through LDS (wrap-around closure included), and each thread then writes
 // the true incoming states of its own segments.  Summaries are loaded PB
-// segments at a time so that their loads are in flight together.
+// segments at a time so that their loads are in flight together; when a
+// thread has at most PB segments, all four words of each are loaded once and
+// kept in registers through both recurrences (one round of loads instead of
+// four, the same arithmetic in the same order).  REG = false keeps the
+// batched loads only (for kernels that have no registers to spare).
 constexpr int PB = 8;
 
 __device__ __forceinline__ void mat2_load(const double *m, Aff &x) {
     x.a = m[0]; x.b = m[1]; x.c = m[2]; x.d = m[3];
 }
 
-template <int BW, int G>
+template <int BW, int G, bool REG = true>
 __device__ __forceinline__ void cols_b_block(const ColsInst *__restrict__ inst, const int *__restrict__ map,
                                              const int blk, Aff *xa) {
     constexpr int kBCols = kColsThreads / G;
@@ -174,6 +192,109 @@ __device__ __forceinline__ void cols_b_block(const ColsInst *__restrict__ inst, 
     mat2_load(I.Qf, Qf);
     mat2_load(I.Ql, Ql);
 
+    if (REG && sp <= PB) {   // uniform
+        const int n = se - sb;
+        double e0[PB], e1[PB], g0[PB], g1[PB], cs0[PB], cs1[PB];
+        if (valid) {
+#pragma unroll
+            for (int u = 0; u < PB; ++u)
+                if (u < n) {
+                    const long long o = static_cast<long long>(sb + u) * 4 * nx;
+                    e0[u] = cy[o];
+                    e1[u] = cy[o + nx];
+                    g0[u] = cy[o + 2 * nx];
+                    g1[u] = cy[o + 3 * nx];
+                }
+        }
+        // forward: c_{s+1} = T_s c_s + e_s
+        Aff m = aff_identity();
+        if (valid) {
+#pragma unroll
+            for (int u = 0; u < PB; ++u)
+                if (u < n) {
+                    Aff x = sb + u == ns - 1 ? Tl : Tf;
+                    x.e0 = e0[u];
+                    x.e1 = e1[u];
+                    m = compose_x(x, m);
+                }
+        }
+        xa[q * kBCols + cl] = m;
+        __syncthreads();
+        Aff pre = aff_identity(), tot = aff_identity();
+#pragma unroll
+        for (int r = 0; r < G; ++r) {
+            const Aff x = xa[r * kBCols + cl];
+            if (r < q) pre = compose_x(x, pre);
+            tot = compose_x(x, tot);
+        }
+        __syncthreads();
+        double x0 = fma(I.Cinv[0], tot.e0, I.Cinv[1] * tot.e1);
+        double x1 = fma(I.Cinv[2], tot.e0, I.Cinv[3] * tot.e1);
+        double c0 = fma(pre.a, x0, fma(pre.b, x1, pre.e0));
+        double c1 = fma(pre.c, x0, fma(pre.d, x1, pre.e1));
+        if (valid) {
+#pragma unroll
+            for (int u = 0; u < PB; ++u)
+                if (u < n) {
+                    const long long o = static_cast<long long>(sb + u) * 4 * nx;
+                    const Aff &T = sb + u == ns - 1 ? Tl : Tf;
+                    cy[o] = c0;
+                    cy[o + nx] = c1;
+                    cs0[u] = c0;
+                    cs1[u] = c1;
+                    const double n0 = fma(T.a, c0, fma(T.b, c1, e0[u]));
+                    const double n1 = fma(T.c, c0, fma(T.d, c1, e1[u]));
+                    c0 = n0;
+                    c1 = n1;
+                }
+        }
+        // backward: d_{s-1} = T_s d_s + g_s + Q_s c_s
+        m = aff_identity();
+        if (valid) {
+#pragma unroll
+            for (int u = PB - 1; u >= 0; --u)
+                if (u < n) {
+                    const int s = sb + u;
+                    const Aff &Q = s == ns - 1 ? Ql : Qf;
+                    Aff x = s == ns - 1 ? Tl : Tf;
+                    x.e0 = fma(Q.a, cs0[u], fma(Q.b, cs1[u], g0[u]));
+                    x.e1 = fma(Q.c, cs0[u], fma(Q.d, cs1[u], g1[u]));
+                    m = compose_x(x, m);
+                }
+        }
+        xa[q * kBCols + cl] = m;
+        __syncthreads();
+        pre = aff_identity();
+        tot = aff_identity();
+#pragma unroll
+        for (int r = G - 1; r >= 0; --r) {
+            const Aff x = xa[r * kBCols + cl];
+            if (r > q) pre = compose_x(x, pre);
+            tot = compose_x(x, tot);
+        }
+        x0 = fma(I.Cinv[0], tot.e0, I.Cinv[1] * tot.e1);
+        x1 = fma(I.Cinv[2], tot.e0, I.Cinv[3] * tot.e1);
+        double d0 = fma(pre.a, x0, fma(pre.b, x1, pre.e0));
+        double d1 = fma(pre.c, x0, fma(pre.d, x1, pre.e1));
+        if (valid) {
+#pragma unroll
+            for (int u = PB - 1; u >= 0; --u)
+                if (u < n) {
+                    const int s = sb + u;
+                    const long long o = static_cast<long long>(s) * 4 * nx;
+                    const Aff &Q = s == ns - 1 ? Ql : Qf;
+                    const Aff &T = s == ns - 1 ? Tl : Tf;
+                    cy[o + 2 * nx] = d0;
+                    cy[o + 3 * nx] = d1;
+                    const double n0 = fma(T.a, d0, fma(T.b, d1, fma(Q.a, cs0[u], fma(Q.b, cs1[u], g0[u]))));
+                    const double n1 = fma(T.c, d0, fma(T.d, d1, fma(Q.c, cs0[u], fma(Q.d, cs1[u], g1[u]))));
+                    d0 = n0;
+                    d1 = n1;
+                }
+        }
+        return;
+    }
+
     // ---- forward: c_{s+1} = T_s c_s + e_s --------------------------------------
     Aff m = aff_identity();
     if (valid) {
@@ -191,7 +312,7 @@ __device__ __forceinline__ void cols_b_block(const ColsInst *__restrict__ inst, 
                     Aff x = s0 + u == ns - 1 ? Tl : Tf;
                     x.e0 = e0[u];
                     x.e1 = e1[u];
-                    m = compose(x, m);
+                    m = compose_x(x, m);
                 }
         }
     }
@@ -201,14 +322,14 @@ __device__ __forceinline__ void cols_b_block(const ColsInst *__restrict__ inst, 
 #pragma unroll
     for (int r = 0; r < G; ++r) {
         const Aff x = xa[r * kBCols + cl];
-        if (r < q) pre = compose(x, pre);
-        tot = compose(x, tot);
+        if (r < q) pre = compose_x(x, pre);
+        tot = compose_x(x, tot);
     }
     __syncthreads();
-    double x0 = I.Cinv[0] * tot.e0 + I.Cinv[1] * tot.e1;
-    double x1 = I.Cinv[2] * tot.e0 + I.Cinv[3] * tot.e1;
-    double c0 = pre.a * x0 + pre.b * x1 + pre.e0;
-    double c1 = pre.c * x0 + pre.d * x1 + pre.e1;
+    double x0 = fma(I.Cinv[0], tot.e0, I.Cinv[1] * tot.e1);
+    double x1 = fma(I.Cinv[2], tot.e0, I.Cinv[3] * tot.e1);
+    double c0 = fma(pre.a, x0, fma(pre.b, x1, pre.e0));
+    double c1 = fma(pre.c, x0, fma(pre.d, x1, pre.e1));
     if (valid) {
         for (int s0 = sb; s0 < se; s0 += PB) {
             double e0[PB], e1[PB];
@@ -224,8 +345,8 @@ __device__ __forceinline__ void cols_b_block(const ColsInst *__restrict__ inst, 
                     const Aff &T = s0 + u == ns - 1 ? Tl : Tf;
                     cy[(s0 + u) * 4 * nx] = c0;
                     cy[(s0 + u) * 4 * nx + nx] = c1;
-                    const double n0 = T.a * c0 + T.b * c1 + e0[u];
-                    const double n1 = T.c * c0 + T.d * c1 + e1[u];
+                    const double n0 = fma(T.a, c0, fma(T.b, c1, e0[u]));
+                    const double n1 = fma(T.c, c0, fma(T.d, c1, e1[u]));
                     c0 = n0;
                     c1 = n1;
                 }
@@ -254,9 +375,9 @@ __device__ __forceinline__ void cols_b_block(const ColsInst *__restrict__ inst, 
                 if (s >= sb) {
                     const Aff &Q = s == ns - 1 ? Ql : Qf;
                     Aff x = s == ns - 1 ? Tl : Tf;
-                    x.e0 = g0[u] + Q.a * cs0[u] + Q.b * cs1[u];
-                    x.e1 = g1[u] + Q.c * cs0[u] + Q.d * cs1[u];
-                    m = compose(x, m);
+                    x.e0 = fma(Q.a, cs0[u], fma(Q.b, cs1[u], g0[u]));
+                    x.e1 = fma(Q.c, cs0[u], fma(Q.d, cs1[u], g1[u]));
+                    m = compose_x(x, m);
                 }
             }
         }
@@ -268,13 +389,13 @@ __device__ __forceinline__ void cols_b_block(const ColsInst *__restrict__ inst, 
 #pragma unroll
     for (int r = G - 1; r >= 0; --r) {
         const Aff x = xa[r * kBCols + cl];
-        if (r > q) pre = compose(x, pre);
-        tot = compose(x, tot);
+        if (r > q) pre = compose_x(x, pre);
+        tot = compose_x(x, tot);
     }
-    x0 = I.Cinv[0] * tot.e0 + I.Cinv[1] * tot.e1;
-    x1 = I.Cinv[2] * tot.e0 + I.Cinv[3] * tot.e1;
-    double d0 = pre.a * x0 + pre.b * x1 + pre.e0;
-    double d1 = pre.c * x0 + pre.d * x1 + pre.e1;
+    x0 = fma(I.Cinv[0], tot.e0, I.Cinv[1] * tot.e1);
+    x1 = fma(I.Cinv[2], tot.e0, I.Cinv[3] * tot.e1);
+    double d0 = fma(pre.a, x0, fma(pre.b, x1, pre.e0));
+    double d1 = fma(pre.c, x0, fma(pre.d, x1, pre.e1));
     if (valid) {
         for (int s1 = se - 1; s1 >= sb; s1 -= PB) {
             double cs0[PB], cs1[PB], g0[PB], g1[PB];
@@ -296,8 +417,8 @@ __device__ __forceinline__ void cols_b_block(const ColsInst *__restrict__ inst, 
                     const Aff &T = s == ns - 1 ? Tl : Tf;
                     cy[s * 4 * nx + 2 * nx] = d0;
                     cy[s * 4 * nx + 3 * nx] = d1;
-                    const double n0 = g0[u] + Q.a * cs0[u] + Q.b * cs1[u] + T.a * d0 + T.b * d1;
-                    const double n1 = g1[u] + Q.c * cs0[u] + Q.d * cs1[u] + T.c * d0 + T.d * d1;
+                    const double n0 = fma(T.a, d0, fma(T.b, d1, fma(Q.a, cs0[u], fma(Q.b, cs1[u], g0[u]))));
+                    const double n1 = fma(T.c, d0, fma(T.d, d1, fma(Q.c, cs0[u], fma(Q.d, cs1[u], g1[u]))));
                     d0 = n0;
                     d1 = n1;
                 }

@@ -116,8 +116,8 @@ __global__ void __launch_bounds__(kPersistThreads, 2) ch_step_persistent(const P
     if (good) {
         Aff *xa = reinterpret_cast<Aff *>(lds);
         for (int b = blockIdx.x; b < p.colsB; b += G) {
-            if (p.bgroups == 16) cols_b_block<2, 16>(p.cols, p.colsB_map, b, xa);
-            else cols_b_block<2, 4>(p.cols, p.colsB_map, b, xa);
+            if (p.bgroups == 16) cols_b_block<2, 16, false>(p.cols, p.colsB_map, b, xa);
+            else cols_b_block<2, 4, false>(p.cols, p.colsB_map, b, xa);
             __syncthreads();
         }
         good = grid_sync(p.bar, p.spin_limit, ok);
