@@ -319,7 +319,7 @@ __device__ __forceinline__ void cols_b_block(const ColsInst *__restrict__ inst, 
     xa[q * kBCols + cl] = m;
     __syncthreads();
     Aff pre = aff_identity(), tot = aff_identity();
-#pragma unroll
+#pragma unroll 4   // bounded: this path serves the persistent kernel, whose registers are full
     for (int r = 0; r < G; ++r) {
         const Aff x = xa[r * kBCols + cl];
         if (r < q) pre = compose_x(x, pre);
@@ -386,7 +386,7 @@ __device__ __forceinline__ void cols_b_block(const ColsInst *__restrict__ inst, 
     __syncthreads();
     pre = aff_identity();
     tot = aff_identity();
-#pragma unroll
+#pragma unroll 4   // bounded: this path serves the persistent kernel, whose registers are full
     for (int r = G - 1; r >= 0; --r) {
         const Aff x = xa[r * kBCols + cl];
         if (r > q) pre = compose_x(x, pre);
