@@ -12,7 +12,7 @@
  *     gcc -O2 -fno-fast-math -ffp-contract=off
  * so that products and sums are rounded separately, in source order.
  *
- * Conventions (readings of the paper, listed in the design doc):
+ * Conventions (readings of the paper where it leaves the choice open):
  *   - grids are row-major, x contiguous: element (j, i) sits at in[j*ld + i]
  *     (x is the contiguous direction and tiles split y, Sec. 2);
  *   - a window with extents left/right (x) and top/bottom (y) has weight
